@@ -1,0 +1,169 @@
+"""ctypes front end of the CPU oracle (plain C, ``nsf_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY. The oracle is the slow, obviously-correct CPU
+statement of the method of Jammy, Jacobs & Sandham (arXiv 1610.09146,
+Sections 2-3) that the GPU library is checked against. Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import this module. It imports nothing from the GPU package.
+
+Arrays are numpy, field-major ``[5][nz][ny][nx]`` (x fastest). ``prec``
+selects the C instantiation: ``"d"`` (float64) or ``"ld"`` (x87 extended,
+``numpy.longdouble``), the latter giving the round-off floor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nsf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+NDIAG = 16
+DIAG_NAMES = [
+    "ke", "enstrophy", "mean_rho", "mean_rhou", "mean_rhov", "mean_rhow", "mean_rhoE",
+    "max_rho", "max_rhou", "max_rhov", "max_rhow", "max_rhoE", "min_rho", "min_p",
+    "nonfinite", "mean_p",
+]
+
+# Low-storage RK3 coefficients (reading of Section 2; the paper names none).
+RK_A = (2.0 / 3.0, 5.0 / 12.0)
+RK_B = (1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-std=gnu11", "-fPIC", "-shared", _SRC, "-o", _LIB + ".tmp", "-lm"]
+        subprocess.check_call(cmd, cwd=_HERE)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        i, d, u64, vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
+        L.oracle_splitmix64.restype = u64
+        L.oracle_splitmix64.argtypes = [u64, u64]
+        L.oracle_splitmix_uniform.restype = d
+        L.oracle_splitmix_uniform.argtypes = [u64, u64]
+        L.oracle_set_threads.argtypes = [i]
+        L.oracle_get_threads.restype = i
+        for s in ("_d", "_ld"):
+            getattr(L, "oracle_init" + s).argtypes = [i, i, i, d, d, d, i, d, u64, d, d, d, vp]
+            getattr(L, "oracle_prims" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+            getattr(L, "oracle_rhs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+            getattr(L, "oracle_rhs_planes" + s).argtypes = [i, i, i, d, d, d, d, vp, vp, i, i]
+            getattr(L, "oracle_rk_step" + s).argtypes = [i, i, i, d, d, d, d, d, i, vp]
+            getattr(L, "oracle_diag" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+            getattr(L, "oracle_derivs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _dtype(prec: str):
+    return {"d": np.float64, "ld": np.longdouble}[prec]
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _phys(phys):
+    return (float(phys["Re"]), float(phys["Ma"]), float(phys["Pr"]), float(phys["gamma"]))
+
+
+def set_threads(n: int) -> None:
+    lib().oracle_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().oracle_get_threads())
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    return int(lib().oracle_splitmix64(seed, counter))
+
+
+def init(shape, phys, tgv, prec: str = "d") -> np.ndarray:
+    """Taylor-Green state q[5][nz][ny][nx] (Section 3)."""
+    nx, ny, nz = shape
+    q = np.zeros((5, nz, ny, nx), dtype=_dtype(prec))
+    ph = tgv.get("phase", (0.0, 0.0, 0.0))
+    getattr(lib(), "oracle_init_" + prec)(
+        nx, ny, nz, float(phys["gamma"]), float(phys["Ma"]), float(tgv.get("V0", 1.0)),
+        int(tgv.get("pert_kind", 0)), float(tgv.get("pert_amp", 0.0)),
+        int(tgv.get("seed", 0)), float(ph[0]), float(ph[1]), float(ph[2]), _ptr(q))
+    return q
+
+
+def _shape_of(q):
+    _, nz, ny, nx = q.shape
+    return nx, ny, nz
+
+
+def prims(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=_dtype(prec))
+    nx, ny, nz = _shape_of(q)
+    out = np.empty_like(q)
+    getattr(lib(), "oracle_prims_" + prec)(nx, ny, nz, *_phys(phys), _ptr(q), _ptr(out))
+    return out
+
+
+def rhs(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
+    """Residual R(q) (Section 2, eqs (1)-(5), (10))."""
+    q = np.ascontiguousarray(q, dtype=_dtype(prec))
+    nx, ny, nz = _shape_of(q)
+    r = np.empty_like(q)
+    getattr(lib(), "oracle_rhs_" + prec)(nx, ny, nz, *_phys(phys), _ptr(q), _ptr(r))
+    return r
+
+
+def rhs_planes(q: np.ndarray, phys, k0: int, k1: int, r: np.ndarray | None = None,
+               prec: str = "d") -> np.ndarray:
+    """Residual on z-planes [k0, k1) only (used to time a bounded sample)."""
+    nx, ny, nz = _shape_of(q)
+    if r is None:
+        r = np.zeros_like(q)
+    getattr(lib(), "oracle_rhs_planes_" + prec)(nx, ny, nz, *_phys(phys), _ptr(q), _ptr(r),
+                                               int(k0), int(k1))
+    return r
+
+
+def rk_step(q: np.ndarray, phys, dt: float, nsteps: int = 1, prec: str = "d") -> np.ndarray:
+    """Advance nsteps low-storage RK3 steps; returns a new array."""
+    q = np.array(q, dtype=_dtype(prec), order="C", copy=True)
+    nx, ny, nz = _shape_of(q)
+    getattr(lib(), "oracle_rk_step_" + prec)(nx, ny, nz, *_phys(phys), float(dt), int(nsteps),
+                                            _ptr(q))
+    return q
+
+
+def diagnostics(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=_dtype(prec))
+    nx, ny, nz = _shape_of(q)
+    out = np.zeros(NDIAG, dtype=np.float64)
+    getattr(lib(), "oracle_diag_" + prec)(nx, ny, nz, *_phys(phys), _ptr(q), _ptr(out))
+    return out
+
+
+def derivs(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
+    """The 60 derivative groups as fields [60][nz][ny][nx] (order documented
+    with oracle_derivs in the C source)."""
+    q = np.ascontiguousarray(q, dtype=_dtype(prec))
+    nx, ny, nz = _shape_of(q)
+    d = np.empty((60, nz, ny, nx), dtype=_dtype(prec))
+    getattr(lib(), "oracle_derivs_" + prec)(nx, ny, nz, *_phys(phys), _ptr(q), _ptr(d))
+    return d
