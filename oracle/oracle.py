@@ -62,6 +62,9 @@ def lib():
         L.oracle_get_threads.restype = i
         for s in ("_d", "_ld"):
             getattr(L, "oracle_init" + s).argtypes = [i, i, i, d, d, d, i, d, u64, d, d, d, vp]
+            getattr(L, "oracle_init_slab" + s).argtypes = [i, i, i, i, i, d, d, d, i, d, u64, d, d,
+                                                          d, vp]
+            getattr(L, "oracle_rhs_slab" + s).argtypes = [i, i, i, i, d, d, d, d, vp, vp]
             getattr(L, "oracle_prims" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
             getattr(L, "oracle_rhs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
             getattr(L, "oracle_rhs_planes" + s).argtypes = [i, i, i, d, d, d, d, vp, vp, i, i]
@@ -107,6 +110,33 @@ def init(shape, phys, tgv, prec: str = "d") -> np.ndarray:
         int(tgv.get("pert_kind", 0)), float(tgv.get("pert_amp", 0.0)),
         int(tgv.get("seed", 0)), float(ph[0]), float(ph[1]), float(ph[2]), _ptr(q))
     return q
+
+
+def init_slab(shape, k0: int, nk: int, phys, tgv, prec: str = "d") -> np.ndarray:
+    """Planes k0 .. k0+nk-1 (periodic) of the Taylor-Green state of an
+    nx x ny x nz grid, as a [5][nk][ny][nx] array."""
+    nx, ny, nz = shape
+    q = np.zeros((5, nk, ny, nx), dtype=_dtype(prec))
+    ph = tgv.get("phase", (0.0, 0.0, 0.0))
+    getattr(lib(), "oracle_init_slab_" + prec)(
+        nx, ny, nz, int(k0), int(nk), float(phys["gamma"]), float(phys["Ma"]),
+        float(tgv.get("V0", 1.0)), int(tgv.get("pert_kind", 0)), float(tgv.get("pert_amp", 0.0)),
+        int(tgv.get("seed", 0)), float(ph[0]), float(ph[1]), float(ph[2]), _ptr(q))
+    return q
+
+
+def rhs_slab(q_slab: np.ndarray, nz_glob: int, phys, prec: str = "d") -> np.ndarray:
+    """Residual on the interior planes 2 .. nzs-3 of a slab of nzs
+    consecutive planes of an nz_glob-plane periodic grid; returns those
+    nzs-4 planes."""
+    q_slab = np.ascontiguousarray(q_slab, dtype=_dtype(prec))
+    _, nzs, ny, nx = q_slab.shape
+    if nzs < 5 or nzs > nz_glob + 4:
+        raise ValueError("slab needs 5 <= nzs <= nz_glob + 4 planes")
+    r = np.zeros_like(q_slab)
+    getattr(lib(), "oracle_rhs_slab_" + prec)(nx, ny, int(nz_glob), nzs, *_phys(phys),
+                                              _ptr(q_slab), _ptr(r))
+    return r[:, 2:nzs - 2]
 
 
 def _shape_of(q):

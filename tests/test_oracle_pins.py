@@ -346,3 +346,19 @@ def test_uniform_translation_convective_terms():
     assert np.max(np.abs(r[0] + U * Drho)) < 1e-13
     assert np.max(np.abs(r[3] + U * U * Drho)) < 1e-13
     assert np.max(np.abs(r[1])) < 1e-15 and np.max(np.abs(r[2])) < 1e-15
+
+
+# ------------------------------------------------------------- slab paths
+def test_slab_entry_points_match_full_grid():
+    # the sampled-plane checks at large grids use slabs cut from the grid;
+    # a slab must reproduce the full-grid values on its interior planes
+    shape = (12, 10, 16)
+    tgv = {"pert_kind": 1, "pert_amp": 0.05, "seed": 21}
+    q = O.init(shape, PHYS, tgv)
+    r = O.rhs(q, PHYS)
+    for k0 in (0, 7, 14):
+        qs = O.init_slab(shape, k0 - 2, 6, PHYS, tgv)
+        idx = [(k % 16) for k in range(k0 - 2, k0 + 4)]
+        assert np.array_equal(qs, q[:, idx])
+        rs = O.rhs_slab(qs, 16, PHYS)
+        assert np.array_equal(rs, r[:, idx[2:4]])
