@@ -1,0 +1,208 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the Navier-Stokes RHS + low-storage RK3 hot path.
+
+Workload (default): the paper's Taylor-Green vortex (Section 3) on a 512^3
+periodic grid in double precision, Re=1600, Ma=0.1, Pr=0.71, dt=4.23125e-4,
+with the kinetic-energy and enstrophy integrals reduced every step in FP64.
+One timed step = one three-stage RK step (3 residual evaluations + stage
+updates) + the diagnostics. The metric is grid-point RHS evaluations per
+second: n^3 * 3 * steps / time, with all state resident in HBM.
+
+Beside the main line it reports the roofline of the dominant kernel (HIP
+events on its launch stream), the other algorithms and the FP32 form at the
+same size, and the CPU oracle timed on a bounded slab of the same grid.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point RHS evals/s and % HBM roofline at 512^3 FP64; FP32/batched vs FP64"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+# Algorithmic HBM bytes per grid point per launch of each kernel family,
+# as (bytes with FP64 fields, bytes with FP32 fields): every input field
+# read once, every output field written once; stencil neighbours are
+# on-chip reuse. The RK accumulator is FP64 in both precisions.
+FAMILY_BYTES = {
+    "prims": (80, 40),            # q -> u, v, w, p, T
+    "update": (160, 120),         # r, q_acc -> q, q_acc
+    "ra_naive": (120, 60),        # q, prims -> r
+    "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
+    "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
+    "bl_deriv": (16, 8),          # one field -> one derivative
+    "bl_product": (24, 12),       # two fields -> one product
+    "bl_assemble": (584, 292),    # 60 derivatives, q, u -> r
+    "diag": (40, 20),             # q -> 16 scalars
+}
+
+VARIANT_FAMILIES = {
+    "BL": ["prims", "bl_product", "bl_deriv", "bl_assemble", "update", "diag"],
+    "RA": ["prims", "ra_naive", "update", "diag"],
+    "SS": ["prims", "ss_grad_naive", "ss_naive", "update", "diag"],
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=1,
+                time_families=True, tune=None):
+    """Time `steps` RK steps (+ diagnostics) of one configuration."""
+    shape = (n, n, n)
+    phys = W.TGV_PHYS
+    dt = W.tgv_dt(n)
+    s = nsf.Solver(shape, phys, variant, precision, tune=tune)
+    s.init(W.tgv_unperturbed())
+    torch.cuda.synchronize()
+    # warmup; also find the family with the largest summed kernel time
+    fam_ms = {}
+    fams = VARIANT_FAMILIES.get(variant, [])
+    for w in range(max(warmup, 1)):
+        s.step(dt, 1)
+        s.diagnostics()
+    if time_families:
+        for fam in fams:
+            nsf.timer_enable(fam)
+            s.step(dt, 1)
+            s.diagnostics()
+            torch.cuda.synchronize()
+            c, ms = nsf.timer_read()
+            fam_ms[fam] = ms
+        nsf.timer_enable(None)
+    dominant = max(fam_ms, key=fam_ms.get) if fam_ms else None
+    if dominant:
+        nsf.timer_enable(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diag = None
+    for k in range(steps):
+        s.step(dt, 1)
+        if diag_every and (k + 1) % diag_every == 0:
+            diag = s.diagnostics()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kcount, kms = nsf.timer_read() if dominant else (0, 0.0)
+    nsf.timer_enable(None)
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    rate = n ** 3 * 3 * steps / (t1 - t0)
+    out = {
+        "variant": variant, "precision": precision, "n": n, "steps": steps,
+        "ms_per_step": ms_per_step, "pt_rhs_per_s": rate, "dominant": dominant,
+        "dominant_launches": kcount, "dominant_ms_total": kms,
+        "family_ms_one_step": fam_ms,
+        "ke": float(diag[0]) if diag is not None else None,
+        "enstrophy": float(diag[1]) if diag is not None else None,
+    }
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(res, precision):
+    fam = res["dominant"]
+    if not fam or res["dominant_launches"] == 0:
+        return None
+    per_pt = FAMILY_BYTES[fam][0 if precision == "f64" else 1]
+    avg_s = res["dominant_ms_total"] / res["dominant_launches"] / 1e3
+    traffic_bytes = per_pt * res["n"] ** 3
+    achieved = traffic_bytes / avg_s / 1e9
+    return {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": traffic_bytes,
+            "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def cpu_baseline(W, budget_s=12.0, n=512, planes_per_call=8):
+    """Oracle (plain C, FP64) residual on consecutive z-slabs of the same
+    512^3 Taylor-Green grid until about budget_s seconds have elapsed."""
+    from oracle import oracle as O
+    phys, tgv = W.TGV_PHYS, W.tgv_unperturbed()
+    threads = O.get_threads()
+    done_pts, spent, k0 = 0, 0.0, 0
+    while spent < budget_s and k0 < n:
+        qs = O.init_slab((n, n, n), k0 - 2, planes_per_call + 4, phys, tgv)
+        t0 = time.perf_counter()
+        O.rhs_slab(qs, n, phys)
+        spent += time.perf_counter() - t0
+        done_pts += planes_per_call * n * n
+        k0 += planes_per_call
+    return {"value": done_pts / spent, "unit": "pt-RHS/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle residual of z-planes 0..{k0 - 1} of the {n}^3 Taylor-Green "
+                      f"grid ({done_pts} point-RHS in {spent:.1f} s, {threads} threads)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--variant", default="RA")
+    ap.add_argument("--no-extras", action="store_true", help="skip BL/SS/FP32 side measurements")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the domain-decomposed form is a design note only); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1610_09146_amd import nsf, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    nsf.lib()  # fail loudly if the HIP library is missing
+    n = args.n
+    log(f"main: {args.variant} f64 n={n} steps={args.steps}")
+    main_res = run_variant(nsf, torch, W, n, args.variant, "f64", args.steps, args.warmup)
+    log(f"main done: {main_res['pt_rhs_per_s']:.3e} pt-RHS/s")
+    extras = {}
+    if not args.no_extras:
+        for v, prec, k in (("BL", "f64", 3), ("SS", "f64", 5), ("RA", "f32", 5)):
+            if v == args.variant and prec == "f64":
+                continue
+            log(f"extra: {v} {prec}")
+            r = run_variant(nsf, torch, W, n, v, prec, k, 1)
+            r["roofline"] = roofline_of(r, prec)
+            extras[f"{v}_{prec}"] = r
+    line = {
+        "metric": METRIC,
+        "value": main_res["pt_rhs_per_s"],
+        "unit": "pt-RHS/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"taylor-green {n}^3 FP64, Re=1600 Ma=0.1 Pr=0.71, "
+                               f"dt={W.tgv_dt(n)}, KE+enstrophy every step",
+                   "variant": args.variant, "n": n, "dt": W.tgv_dt(n), "diag_every": 1},
+        "roofline": roofline_of(main_res, "f64"),
+        "main": main_res,
+        "extras": extras,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

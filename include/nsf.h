@@ -1,0 +1,181 @@
+/*
+ * nsf.h -- C ABI of the MI355X (gfx950) library for the explicit
+ * finite-difference compressible Navier-Stokes hot path of Jammy, Jacobs &
+ * Sandham, "Performance evaluation of explicit finite difference algorithms
+ * with varying amounts of computational and memory intensity"
+ * (arXiv 1610.09146).
+ *
+ * What the library computes (paper Section 2):
+ *   - the residual R(q) of the 3D compressible Navier-Stokes equations with
+ *     constant viscosity, eqs (1)-(3), stress eq (4), heat flux eq (5),
+ *     pressure and temperature eqs (6)-(9); convective terms in the
+ *     skew-symmetric form eq (10); viscous terms expanded to second
+ *     derivatives; fourth-order central differences on a periodic grid;
+ *   - the three-stage low-storage Runge-Kutta time advance (Figure 1);
+ *   - in the paper's derivative-storage algorithms BL, RA, SN, RS, SS
+ *     (Section 2, one paragraph each);
+ *   - the Taylor-Green initial state and the kinetic-energy and enstrophy
+ *     integrals of Section 3.
+ *
+ * Conventions shared by every entry point
+ *   - Layout: a field is nz*ny*nx contiguous elements, x fastest
+ *     (index (k*ny + j)*nx + i, point x_i = 2*pi*i/nx, same for y and z).
+ *     A state q is five consecutive fields rho, rho*u, rho*v, rho*w, rho*E.
+ *   - Precision: NSF_F64 -> q, r are double; NSF_F32 -> q, r are float
+ *     (fields and stencil arithmetic in single precision). The Runge-Kutta
+ *     accumulator q_acc and all reductions are always double.
+ *   - Memory: every pointer argument named q, q_acc, r, work is device
+ *     memory owned by the caller; the library only borrows it for the call
+ *     and allocates no device memory outside nsf_batch_create.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
+ *     stream). Calls enqueue work and return without waiting, except where
+ *     stated (diagnostics, autotune, batch diagnostics).
+ *   - Errors: every call returns an nsf_status. Arguments are validated
+ *     before anything is enqueued; on a non-zero return nothing was
+ *     enqueued unless the code is NSF_EHIP. nsf_last_error() gives text.
+ *   - Thread safety: calls are reentrant; the kernel timer
+ *     (nsf_timer_*) is process-global.
+ */
+#ifndef NSF_H
+#define NSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NSF_OK = 0,
+    NSF_EINVAL = -1,       /* bad argument, size or pointer            */
+    NSF_EWORKSPACE = -2,   /* work buffer smaller than required        */
+    NSF_EHIP = -3,         /* HIP runtime or launch error              */
+    NSF_EUNSUPPORTED = -4, /* combination not provided by this build   */
+    NSF_ENONFINITE = -5    /* diagnostics found NaN/Inf in the state   */
+} nsf_status;
+
+/* The paper's algorithms (Section 2):
+ *   NSF_BL  baseline: every first/second derivative is a grid-sized work
+ *           array; products staged in one reused work array; primitives in
+ *           three separate loops (u_i, then p by eq (6), then T by eq (7)).
+ *   NSF_RA  recompute all: no derivative arrays; every derivative occurrence
+ *           is its finite-difference formula; p, T by eqs (8)-(9).
+ *   NSF_SN  store none: as RA, each derivative evaluated once into a
+ *           thread-local value and reused.
+ *   NSF_RS  recompute some: the nine velocity gradients du_i/dx_j stored in
+ *           work arrays, the rest recomputed inline.
+ *   NSF_SS  store some: as RS, the non-stored derivatives held in
+ *           thread-local values (the paper's fastest CPU algorithm). */
+typedef enum { NSF_BL = 0, NSF_RA = 1, NSF_SS = 2, NSF_SN = 3, NSF_RS = 4 } nsf_variant;
+typedef enum { NSF_F64 = 0, NSF_F32 = 1 } nsf_precision;
+
+#define NSF_NDIAG 16
+
+/* Grid: points per axis on the periodic cube [0, 2*pi)^3 (Section 3).
+ * Each n must be >= 5 (distinct radius-2 wrap neighbours) and
+ * nx*ny*nz <= 2^31. */
+typedef struct { int32_t nx, ny, nz; } nsf_grid;
+
+/* Non-dimensional parameters of eqs (4)-(7): Reynolds, Mach, Prandtl
+ * numbers and ratio of specific heats. Re, Ma, Pr > 0, gamma > 1. */
+typedef struct { double Re, Ma, Pr, gamma; } nsf_phys;
+
+/* Taylor-Green initial state (Section 3, after DeBonis 2013):
+ *   u = V0 sin x cos y cos z, v = -V0 cos x sin y cos z, w = 0,
+ *   p = 1/(gamma Ma^2) + V0^2 (cos 2x + cos 2y)(cos 2z + 2)/16, T = 1.
+ * pert_kind 0: none.
+ * pert_kind 1: u_a *= 1 + pert_amp*(2U - 1), U uniform in [0,1) from the
+ *              SplitMix64 stream of `seed` at counter a*npts + point index
+ *              (output number counter + 1).
+ * pert_kind 2: velocity += pert_amp * (sin(x+f0)cos(y+f1)cos(z+f2),
+ *              -cos(x+f0)sin(y+f1)cos(z+f2), 0) with f = phase[]. */
+typedef struct {
+    double V0;
+    double pert_amp;
+    uint64_t seed;
+    int32_t pert_kind;
+    int32_t reserved;
+    double phase[3];
+} nsf_tgv;
+
+/* Implementation knobs (not part of the method). Pass NULL for defaults.
+ *   block_x, block_y: x-y tile of the stencil kernels (0 = default);
+ *   zchunk: planes marched per workgroup by the z-sweeping kernels (0 = default);
+ *   fuse: RA/SN only. 0 = primitives stored by their own kernel and the RK
+ *         update a separate kernel, as in the paper; 1 = primitives
+ *         recomputed inside the residual tile and the RK update fused into
+ *         the residual kernel (needs the ping-pong copy of q in `work`).
+ *   naive: 1 = use the untiled per-point kernels (reference GPU path). */
+typedef struct {
+    int32_t block_x, block_y, zchunk, fuse, naive;
+    int32_t reserved[3];
+} nsf_tuning;
+
+const char *nsf_status_string(int status);
+const char *nsf_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int nsf_version(void);
+
+/* Bytes of `work` needed by nsf_rhs / nsf_rk_step / nsf_diagnostics for this
+ * grid, algorithm, precision and tuning (tuning may be NULL): primitive
+ * fields, stored derivative arrays of the algorithm, the ping-pong state of
+ * the fused form, and reduction scratch. Written to *bytes. */
+int nsf_workspace_bytes(const nsf_grid *g, int variant, int precision,
+                        const nsf_tuning *tune, size_t *bytes);
+
+/* Write the Taylor-Green state (Section 3) to q (precision dtype, 5 fields)
+ * and, if q_acc != NULL, its double-precision value to q_acc (5 fields).
+ * Asynchronous on `stream`. */
+int nsf_init_fields(const nsf_grid *g, const nsf_phys *phys, const nsf_tgv *tgv,
+                    int precision, void *q, double *q_acc, void *stream);
+
+/* r = R(q): the residual of eqs (1)-(3) (Section 2) evaluated with
+ * algorithm `variant`. q is read-only; r (5 fields, same dtype as q) must
+ * not overlap q or work. Asynchronous. */
+int nsf_rhs(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
+            const nsf_tuning *tune, const void *q, void *r, void *work,
+            size_t work_bytes, void *stream);
+
+/* Advance nsteps steps of the three-stage low-storage Runge-Kutta scheme
+ * (Section 2, Figure 1) with time step dt: for substep s = 1..3,
+ *   r = R(q); q = q_acc + A_s dt r (s < 3); q_acc = q_acc + B_s dt r;
+ * then q = q_acc; A = (2/3, 5/12), B = (1/4, 3/20, 3/5).
+ * On entry q_acc must hold the state (double) and q its value in the
+ * precision dtype; on return both hold the new state. r is a 5-field
+ * scratch in the precision dtype. Asynchronous. */
+int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
+                const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
+                double *q_acc, void *r, void *work, size_t work_bytes, void *stream);
+
+/* Diagnostics of q (Section 3: kinetic-energy and enstrophy integrals),
+ * reduced in double in a fixed order (bitwise reproducible). Waits for the
+ * stream, then fills out[NSF_NDIAG] (host memory):
+ *   0 KE = <rho|u|^2/2>   1 enstrophy = <rho|curl u|^2/2> (curl by the
+ *   fourth-order first derivative)   2..6 <q_f>   7..11 max|q_f|
+ *   12 min rho   13 min p   14 number of non-finite values in q   15 <p>
+ * where <.> is the mean over grid points (volume integral / (2 pi)^3).
+ * Returns NSF_ENONFINITE (after filling out) if out[14] > 0. */
+int nsf_diagnostics(const nsf_grid *g, const nsf_phys *phys, int precision,
+                    const void *q, void *work, size_t work_bytes, double *out,
+                    void *stream);
+
+/* Device-to-device copy of `bytes` with a plain streaming kernel; used to
+ * calibrate achievable HBM bandwidth and the memory counters. */
+int nsf_device_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+/* Kernel timer for roofline reporting. nsf_timer_enable(name) records a
+ * HIP event pair around every launch of the kernel family `name` (see
+ * nsf_timer_names), on the stream it is launched on; NULL disables it and
+ * discards the records. nsf_timer_read waits for the recorded events and
+ * returns the launch count and the summed duration in milliseconds. */
+int nsf_timer_enable(const char *name);
+int nsf_timer_read(int64_t *count, double *total_ms);
+/* Comma-separated list of kernel family names known to the timer. */
+const char *nsf_timer_names(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NSF_H */

@@ -1,0 +1,431 @@
+// C ABI of the library (declared in include/nsf.h): argument validation,
+// workspace layout, the per-algorithm kernel sequences of one residual
+// evaluation and the low-storage RK time loop (paper Section 2, Figure 1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/nsf.h"
+#include "nsf_internal.h"
+
+namespace nsf {
+
+// ------------------------------------------------------------ error text
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_hip(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(NSF_EHIP, "%s: %s", where, hipGetErrorString(e));
+    return NSF_OK;
+}
+}  // namespace
+
+// ------------------------------------------------------------ kernel timer
+namespace {
+struct Timer {
+    std::mutex mu;
+    std::string family;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+};
+Timer& timer() {
+    static Timer* t = new Timer();  // intentionally never destroyed
+    return *t;
+}
+}  // namespace
+
+TimerScope::TimerScope(const char* family, hipStream_t s) : on(false), stream(s) {
+    Timer& t = timer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (t.family.empty() || t.family != family) return;
+    if (t.used == t.ev.size()) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+        t.ev.emplace_back(a, b);
+    }
+    if (hipEventRecord(t.ev[t.used].first, s) != hipSuccess) return;
+    on = true;
+}
+
+TimerScope::~TimerScope() {
+    if (!on) return;
+    Timer& t = timer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (hipEventRecord(t.ev[t.used].second, stream) == hipSuccess) ++t.used;
+}
+
+// ------------------------------------------------------------ constants
+template <typename T>
+Coef<T> make_coef(const Dims& d, double Re, double Ma, double Pr, double gamma) {
+    Coef<T> c;
+    const int n[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) {
+        const double h = 2.0 * M_PI / (double)n[a];
+        c.a1[a] = (T)(8.0 / (12.0 * h));
+        c.a2[a] = (T)(-1.0 / (12.0 * h));
+        c.b0[a] = (T)(-30.0 / (12.0 * h * h));
+        c.b1[a] = (T)(16.0 / (12.0 * h * h));
+        c.b2[a] = (T)(-1.0 / (12.0 * h * h));
+    }
+    c.inv_Re = (T)(1.0 / Re);
+    c.third = (T)(1.0 / 3.0);
+    c.two_thirds = (T)(2.0 / 3.0);
+    c.gm1 = (T)(gamma - 1.0);
+    c.gM2 = (T)(gamma * Ma * Ma);
+    c.kappa = (T)(1.0 / ((gamma - 1.0) * Ma * Ma * Pr * Re));
+    return c;
+}
+template Coef<float> make_coef<float>(const Dims&, double, double, double, double);
+template Coef<double> make_coef<double>(const Dims&, double, double, double, double);
+
+// ------------------------------------------------------------ layout
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t prim = 0, deriv = 0, prod = 0, diag_partial = 0, diag_out = 0, total = 0;
+    int nderiv = 0;
+};
+
+bool is_variant(int v) { return v >= NSF_BL && v <= NSF_RS; }
+bool is_precision(int p) { return p == NSF_F64 || p == NSF_F32; }
+
+int deriv_arrays(int variant) {
+    switch (variant) {
+        case NSF_BL: return 60;
+        case NSF_SS:
+        case NSF_RS: return 9;
+        default: return 0;
+    }
+}
+
+Layout layout_for(const Dims& d, int variant, int precision) {
+    const size_t es = precision == NSF_F32 ? 4 : 8;
+    Layout L;
+    size_t off = 0;
+    L.prim = off;
+    off = align_up(off + 5 * d.npts * es);
+    L.nderiv = deriv_arrays(variant);
+    L.deriv = off;
+    off = align_up(off + (size_t)L.nderiv * d.npts * es);
+    L.prod = off;
+    off = align_up(off + (variant == NSF_BL ? d.npts * es : 0));
+    L.diag_partial = off;
+    off = align_up(off + diag_partial_count(d) * NSF_NDIAG * sizeof(double));
+    L.diag_out = off;
+    off = align_up(off + NSF_NDIAG * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+int validate_grid(const nsf_grid* g, Dims* d) {
+    if (!g) return fail(NSF_EINVAL, "grid is NULL");
+    if (g->nx < 5 || g->ny < 5 || g->nz < 5)
+        return fail(NSF_EINVAL, "grid %dx%dx%d: every axis needs >= 5 points", g->nx, g->ny, g->nz);
+    const size_t n = (size_t)g->nx * g->ny * g->nz;
+    if (n > (size_t)1 << 31) return fail(NSF_EINVAL, "grid has %zu points, limit 2^31", n);
+    d->nx = g->nx;
+    d->ny = g->ny;
+    d->nz = g->nz;
+    d->npts = n;
+    return NSF_OK;
+}
+
+int validate_phys(const nsf_phys* p) {
+    if (!p) return fail(NSF_EINVAL, "phys is NULL");
+    if (!(p->Re > 0) || !(p->Ma > 0) || !(p->Pr > 0) || !(p->gamma > 1) || !std::isfinite(p->Re) ||
+        !std::isfinite(p->Ma) || !std::isfinite(p->Pr) || !std::isfinite(p->gamma))
+        return fail(NSF_EINVAL, "phys: need finite Re, Ma, Pr > 0 and gamma > 1");
+    return NSF_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+// One residual evaluation r = R(q) with algorithm `variant`.
+template <typename T>
+int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tune, const T* q,
+             T* r, char* work, const Layout& L, hipStream_t s) {
+    (void)tune;
+    const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
+    T* prim = (T*)(work + L.prim);
+    const size_t n = d.npts;
+    const T* rho = q;
+    const T* m[3] = {q + n, q + 2 * n, q + 3 * n};
+    const T* E = q + 4 * n;
+    const T* vel[3] = {prim, prim + n, prim + 2 * n};
+    const T* p = prim + 3 * n;
+    const T* Tt = prim + 4 * n;
+    switch (variant) {
+        case NSF_BL: {
+            // primitives in three loops, then one loop per derivative
+            launch_prims_bl<T>(d, c, q, prim, s);
+            T* dv = (T*)(work + L.deriv);
+            T* prod = (T*)(work + L.prod);
+            auto D = [&](int idx) { return dv + (size_t)idx * n; };
+            for (int b = 0; b < 3; ++b) {
+                launch_bl_deriv<T>(d, c, b, 1, rho, D(0 + b), s);
+                launch_bl_deriv<T>(d, c, b, 1, E, D(12 + b), s);
+                launch_bl_deriv<T>(d, c, b, 1, p, D(39 + b), s);
+                launch_bl_deriv<T>(d, c, b, 2, Tt, D(57 + b), s);
+                for (int a = 0; a < 3; ++a) {
+                    launch_bl_deriv<T>(d, c, b, 1, m[a], D(3 + 3 * a + b), s);
+                    launch_bl_deriv<T>(d, c, b, 1, vel[a], D(15 + 3 * a + b), s);
+                    launch_bl_deriv<T>(d, c, b, 2, vel[a], D(42 + 3 * a + b), s);
+                    launch_product<T>(d, m[a], vel[b], prod, s);
+                    launch_bl_deriv<T>(d, c, b, 1, prod, D(24 + 3 * a + b), s);
+                }
+                launch_product<T>(d, E, vel[b], prod, s);
+                launch_bl_deriv<T>(d, c, b, 1, prod, D(33 + b), s);
+                launch_product<T>(d, p, vel[b], prod, s);
+                launch_bl_deriv<T>(d, c, b, 1, prod, D(36 + b), s);
+            }
+            // cross derivatives D_a(G_kk) from the stored diagonal gradients
+            const int pairs[6][2] = {{0, 1}, {0, 2}, {1, 0}, {1, 2}, {2, 0}, {2, 1}};
+            for (int t = 0; t < 6; ++t) {
+                const int a = pairs[t][0], kk = pairs[t][1];
+                launch_bl_deriv<T>(d, c, a, 1, D(15 + 4 * kk), D(51 + t), s);
+            }
+            launch_bl_assemble<T>(d, c, q, prim, dv, r, s);
+            break;
+        }
+        case NSF_RA:
+        case NSF_SN:
+            launch_prims<T>(d, c, q, prim, s);
+            launch_ra_naive<T>(d, c, q, prim, r, s);
+            break;
+        case NSF_SS:
+        case NSF_RS: {
+            T* grad = (T*)(work + L.deriv);
+            launch_prims<T>(d, c, q, prim, s);
+            launch_ss_grad_naive<T>(d, c, prim, grad, s);
+            launch_ss_naive<T>(d, c, q, prim, grad, r, s);
+            break;
+        }
+        default:
+            return fail(NSF_EUNSUPPORTED, "variant %d", variant);
+    }
+    return check_hip("rhs launch");
+}
+
+template <typename T>
+int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tune, double dt,
+            int nsteps, T* q, double* qacc, T* r, char* work, const Layout& L, hipStream_t s) {
+    static const double A[2] = {2.0 / 3.0, 5.0 / 12.0};
+    static const double B[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
+    for (int step = 0; step < nsteps; ++step) {
+        for (int st = 0; st < 3; ++st) {
+            int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s);
+            if (rc) return rc;
+            StageCoef sc;
+            sc.a_dt = st < 2 ? A[st] * dt : 0.0;
+            sc.b_dt = B[st] * dt;
+            sc.last = st == 2;
+            launch_update<T>(d, sc, r, q, qacc, s);
+        }
+    }
+    return check_hip("rk_step launch");
+}
+
+}  // namespace
+}  // namespace nsf
+
+using namespace nsf;
+
+extern "C" {
+
+const char* nsf_status_string(int status) {
+    switch (status) {
+        case NSF_OK: return "NSF_OK";
+        case NSF_EINVAL: return "NSF_EINVAL: invalid argument";
+        case NSF_EWORKSPACE: return "NSF_EWORKSPACE: work buffer too small";
+        case NSF_EHIP: return "NSF_EHIP: HIP runtime error";
+        case NSF_EUNSUPPORTED: return "NSF_EUNSUPPORTED: not supported";
+        case NSF_ENONFINITE: return "NSF_ENONFINITE: non-finite values in state";
+        default: return "unknown nsf status";
+    }
+}
+
+const char* nsf_last_error(void) { return g_err.c_str(); }
+
+int nsf_version(void) { return 100; }
+
+int nsf_workspace_bytes(const nsf_grid* g, int variant, int precision, const nsf_tuning* tune,
+                        size_t* bytes) {
+    (void)tune;
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!bytes) return fail(NSF_EINVAL, "bytes is NULL");
+    *bytes = layout_for(d, variant, precision).total;
+    return NSF_OK;
+}
+
+int nsf_init_fields(const nsf_grid* g, const nsf_phys* phys, const nsf_tgv* tgv, int precision,
+                    void* q, double* q_acc, void* stream) {
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if ((rc = validate_phys(phys))) return rc;
+    if (!tgv) return fail(NSF_EINVAL, "tgv is NULL");
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!q) return fail(NSF_EINVAL, "q is NULL");
+    if (tgv->pert_kind < 0 || tgv->pert_kind > 2) return fail(NSF_EINVAL, "pert_kind %d", tgv->pert_kind);
+    if (!std::isfinite(tgv->V0) || !std::isfinite(tgv->pert_amp)) return fail(NSF_EINVAL, "tgv values not finite");
+    InitParams p;
+    p.gamma = phys->gamma;
+    p.Ma = phys->Ma;
+    p.V0 = tgv->V0;
+    p.amp = tgv->pert_amp;
+    p.seed = tgv->seed;
+    p.kind = tgv->pert_kind;
+    for (int a = 0; a < 3; ++a) p.phase[a] = tgv->phase[a];
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == NSF_F64) launch_init<double>(d, p, (double*)q, q_acc, s);
+    else launch_init<float>(d, p, (float*)q, q_acc, s);
+    return check_hip("init launch");
+}
+
+int nsf_rhs(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
+            const nsf_tuning* tune, const void* q, void* r, void* work, size_t work_bytes,
+            void* stream) {
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if ((rc = validate_phys(phys))) return rc;
+    if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!q || !r || !work) return fail(NSF_EINVAL, "q, r and work must be non-NULL");
+    const Layout L = layout_for(d, variant, precision);
+    if (work_bytes < L.total)
+        return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
+    const size_t fb = 5 * d.npts * (precision == NSF_F32 ? 4 : 8);
+    if (overlap(q, fb, r, fb) || overlap(r, fb, work, L.total) || overlap(q, fb, work, L.total))
+        return fail(NSF_EINVAL, "q, r and work must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == NSF_F64)
+        return rhs_impl<double>(d, phys, variant, tune, (const double*)q, (double*)r, (char*)work, L, s);
+    return rhs_impl<float>(d, phys, variant, tune, (const float*)q, (float*)r, (char*)work, L, s);
+}
+
+int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
+                const nsf_tuning* tune, double dt, int32_t nsteps, void* q, double* q_acc,
+                void* r, void* work, size_t work_bytes, void* stream) {
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if ((rc = validate_phys(phys))) return rc;
+    if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!q || !q_acc || !r || !work) return fail(NSF_EINVAL, "q, q_acc, r and work must be non-NULL");
+    if (nsteps < 0) return fail(NSF_EINVAL, "nsteps %d", nsteps);
+    if (!std::isfinite(dt)) return fail(NSF_EINVAL, "dt not finite");
+    const Layout L = layout_for(d, variant, precision);
+    if (work_bytes < L.total)
+        return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
+    const size_t fb = 5 * d.npts * (precision == NSF_F32 ? 4 : 8);
+    const size_t ab = 5 * d.npts * sizeof(double);
+    if (overlap(q, fb, r, fb) || overlap(q, fb, q_acc, ab) || overlap(r, fb, q_acc, ab) ||
+        overlap(q, fb, work, L.total) || overlap(r, fb, work, L.total) ||
+        overlap(q_acc, ab, work, L.total))
+        return fail(NSF_EINVAL, "q, q_acc, r and work must not overlap");
+    hipStream_t s = (hipStream_t)stream;
+    if (precision == NSF_F64)
+        return rk_impl<double>(d, phys, variant, tune, dt, nsteps, (double*)q, q_acc, (double*)r,
+                               (char*)work, L, s);
+    return rk_impl<float>(d, phys, variant, tune, dt, nsteps, (float*)q, q_acc, (float*)r,
+                          (char*)work, L, s);
+}
+
+int nsf_diagnostics(const nsf_grid* g, const nsf_phys* phys, int precision, const void* q,
+                    void* work, size_t work_bytes, double* out, void* stream) {
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if ((rc = validate_phys(phys))) return rc;
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!q || !work || !out) return fail(NSF_EINVAL, "q, work and out must be non-NULL");
+    // the diagnostics region is the tail of every layout; RA's is the smallest
+    const Layout L = layout_for(d, NSF_RA, precision);
+    if (work_bytes < L.total)
+        return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char* w = (char*)work;
+    const Coef<double> c = make_coef<double>(d, phys->Re, phys->Ma, phys->Pr, phys->gamma);
+    double* partial = (double*)(w + L.diag_partial);
+    double* dout = (double*)(w + L.diag_out);
+    if (precision == NSF_F64) launch_diag<double>(d, c, (const double*)q, partial, dout, s);
+    else launch_diag<float>(d, c, (const float*)q, partial, dout, s);
+    if ((rc = check_hip("diagnostics launch"))) return rc;
+    hipError_t e = hipMemcpyAsync(out, dout, NSF_NDIAG * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(NSF_EHIP, "diagnostics copy: %s", hipGetErrorString(e));
+    if (out[14] > 0) return fail(NSF_ENONFINITE, "%.0f non-finite values in q", out[14]);
+    return NSF_OK;
+}
+
+int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
+    if (!src || !dst) return fail(NSF_EINVAL, "src and dst must be non-NULL");
+    if (overlap(src, bytes, dst, bytes)) return fail(NSF_EINVAL, "src and dst overlap");
+    launch_copy(src, dst, bytes, (hipStream_t)stream);
+    return check_hip("copy launch");
+}
+
+static const char* kTimerNames =
+    "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ss_grad_naive,ss_naive,diag,copy";
+
+const char* nsf_timer_names(void) { return kTimerNames; }
+
+int nsf_timer_enable(const char* name) {
+    Timer& t = timer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.family = name ? name : "";
+    t.used = 0;
+    return NSF_OK;
+}
+
+int nsf_timer_read(int64_t* count, double* total_ms) {
+    if (!count || !total_ms) return fail(NSF_EINVAL, "count and total_ms must be non-NULL");
+    Timer& t = timer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    double ms = 0.0;
+    for (size_t i = 0; i < t.used; ++i) {
+        hipError_t e = hipEventSynchronize(t.ev[i].second);
+        float x = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&x, t.ev[i].first, t.ev[i].second);
+        if (e != hipSuccess) return fail(NSF_EHIP, "timer read: %s", hipGetErrorString(e));
+        ms += x;
+    }
+    *count = (int64_t)t.used;
+    *total_ms = ms;
+    return NSF_OK;
+}
+
+}  // extern "C"

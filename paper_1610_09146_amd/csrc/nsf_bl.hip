@@ -1,0 +1,127 @@
+// BL (baseline) algorithm kernels (paper Section 2, BL paragraph): each
+// derivative is its own grid loop writing a grid-sized work array, and the
+// residual loop reads the 60 stored derivatives back.
+//
+// Work-array numbering of the 60 derivatives (G_ab = D_b u_a):
+//    0.. 2 D_b rho          3..11 D_b(rho u_a)       12..14 D_b(rho E)
+//   15..23 G_ab             24..32 D_b(rho u_a u_b)  33..35 D_b(rho E u_b)
+//   36..38 D_b(p u_b)       39..41 D_b p             42..50 D2_b u_a
+//   51..56 D_a(G_kk), (a,k) = (0,1),(0,2),(1,0),(1,2),(2,0),(2,1)
+//   57..59 D2_b T
+// (index 3a + b within each nine-array group).
+#include "nsf_internal.h"
+
+namespace nsf {
+
+namespace {
+
+constexpr int kBX = 64, kBY = 4;
+
+// One derivative loop: out = D_AX f (ORDER 1) or D2_AX f (ORDER 2).
+template <typename T, int AX, int ORDER>
+__global__ void __launch_bounds__(kBX * kBY) k_bl_deriv(Dims d, Coef<T> c, const T* __restrict__ f,
+                                                        T* __restrict__ out) {
+    const int i = blockIdx.x * kBX + threadIdx.x;
+    const int j = blockIdx.y * kBY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= d.nx || j >= d.ny) return;
+    const size_t sx = 1, sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
+    const size_t base = (size_t)k * sz + (size_t)j * sy;
+    T v[5];
+#pragma unroll
+    for (int m = -2; m <= 2; ++m) {
+        size_t idx;
+        if (AX == 0) idx = base + wrap(i + m, d.nx) * sx;
+        else if (AX == 1) idx = (size_t)k * sz + (size_t)wrap(j + m, d.ny) * sy + i;
+        else idx = (size_t)wrap(k + m, d.nz) * sz + (size_t)j * sy + i;
+        v[m + 2] = (ORDER == 2 || m != 0) ? f[idx] : T(0);
+    }
+    const size_t o = base + i;
+    if (ORDER == 1) out[o] = d1(v[0], v[1], v[3], v[4], c.a1[AX], c.a2[AX]);
+    else out[o] = d2(v[0], v[1], v[2], v[3], v[4], c.b0[AX], c.b1[AX], c.b2[AX]);
+}
+
+// Residual loop of BL: every derivative read from its work array.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bl_assemble(Dims d, Coef<T> c, const T* __restrict__ q,
+                                                     const T* __restrict__ prim,
+                                                     const T* __restrict__ dv, T* __restrict__ r) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= d.npts) return;
+    const size_t n = d.npts;
+    Center<T> ce;
+    ce.rho = q[e];
+    ce.m[0] = q[n + e];
+    ce.m[1] = q[2 * n + e];
+    ce.m[2] = q[3 * n + e];
+    ce.E = q[4 * n + e];
+    ce.u[0] = prim[e];
+    ce.u[1] = prim[n + e];
+    ce.u[2] = prim[2 * n + e];
+    Terms<T> t;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        t.Drho[b] = dv[(0 + b) * n + e];
+        t.DE[b] = dv[(12 + b) * n + e];
+        t.DEu[b] = dv[(33 + b) * n + e];
+        t.Dpu[b] = dv[(36 + b) * n + e];
+        t.Dp[b] = dv[(39 + b) * n + e];
+        t.D2T[b] = dv[(57 + b) * n + e];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            t.Dm[a][b] = dv[(3 + 3 * a + b) * n + e];
+            t.G[a][b] = dv[(15 + 3 * a + b) * n + e];
+            t.Dmu[a][b] = dv[(24 + 3 * a + b) * n + e];
+            t.D2u[a][b] = dv[(42 + 3 * a + b) * n + e];
+        }
+    }
+    t.cross[0] = dv[51 * n + e] + dv[52 * n + e];
+    t.cross[1] = dv[53 * n + e] + dv[54 * n + e];
+    t.cross[2] = dv[55 * n + e] + dv[56 * n + e];
+    T R[5];
+    assemble(ce, t, c, R);
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r[f * n + e] = R[f];
+}
+
+template <typename T, int AX, int ORDER>
+void launch_one(const Dims& d, const Coef<T>& c, const T* f, T* out, hipStream_t s) {
+    const dim3 g((unsigned)((d.nx + kBX - 1) / kBX), (unsigned)((d.ny + kBY - 1) / kBY), (unsigned)d.nz);
+    hipLaunchKernelGGL((k_bl_deriv<T, AX, ORDER>), g, dim3(kBX, kBY), 0, s, d, c, f, out);
+}
+
+}  // namespace
+
+template <typename T>
+void launch_bl_deriv(const Dims& d, const Coef<T>& c, int axis, int order, const T* f, T* out,
+                     hipStream_t s) {
+    TimerScope ts("bl_deriv", s);
+    if (order == 1) {
+        if (axis == 0) launch_one<T, 0, 1>(d, c, f, out, s);
+        else if (axis == 1) launch_one<T, 1, 1>(d, c, f, out, s);
+        else launch_one<T, 2, 1>(d, c, f, out, s);
+    } else {
+        if (axis == 0) launch_one<T, 0, 2>(d, c, f, out, s);
+        else if (axis == 1) launch_one<T, 1, 2>(d, c, f, out, s);
+        else launch_one<T, 2, 2>(d, c, f, out, s);
+    }
+}
+
+template <typename T>
+void launch_bl_assemble(const Dims& d, const Coef<T>& c, const T* q, const T* prim,
+                        const T* deriv, T* r, hipStream_t s) {
+    TimerScope ts("bl_assemble", s);
+    const unsigned blocks = (unsigned)((d.npts + 255) / 256);
+    hipLaunchKernelGGL(k_bl_assemble<T>, dim3(blocks), dim3(256), 0, s, d, c, q, prim, deriv, r);
+}
+
+#define NSF_INST(T)                                                                             \
+    template void launch_bl_deriv<T>(const Dims&, const Coef<T>&, int, int, const T*, T*,      \
+                                     hipStream_t);                                             \
+    template void launch_bl_assemble<T>(const Dims&, const Coef<T>&, const T*, const T*,       \
+                                        const T*, T*, hipStream_t);
+NSF_INST(float)
+NSF_INST(double)
+#undef NSF_INST
+
+}  // namespace nsf

@@ -1,0 +1,75 @@
+// Host-side launch interface between the C ABI (nsf_api.cpp) and the kernel
+// translation units. Not exported from the shared library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "nsf_device.h"
+
+namespace nsf {
+
+struct InitParams {
+    double gamma, Ma, V0, amp;
+    uint64_t seed;
+    int kind;
+    double phase[3];
+};
+
+// Low-storage RK3 substep coefficients (see nsf_rk_step).
+struct StageCoef {
+    double a_dt;  // A_s dt (unused on the last substep)
+    double b_dt;  // B_s dt
+    int last;     // 1 on the third substep: q = q_acc after the update
+};
+
+// Launch-time kernel timer (nsf_timer_*): brackets launches of the enabled
+// kernel family with HIP events on the launch stream.
+struct TimerScope {
+    TimerScope(const char* family, hipStream_t s);
+    ~TimerScope();
+    bool on;
+    hipStream_t stream;
+};
+
+template <typename T>
+Coef<T> make_coef(const Dims& d, double Re, double Ma, double Pr, double gamma);
+
+// pointwise kernels (nsf_pointwise.hip)
+template <typename T>
+void launch_init(const Dims& d, const InitParams& p, T* q, double* qacc, hipStream_t s);
+template <typename T>
+void launch_prims(const Dims& d, const Coef<T>& c, const T* q, T* prim, hipStream_t s);
+template <typename T>
+void launch_prims_bl(const Dims& d, const Coef<T>& c, const T* q, T* prim, hipStream_t s);
+template <typename T>
+void launch_update(const Dims& d, const StageCoef& sc, const T* r, T* q, double* qacc,
+                   hipStream_t s);
+template <typename T>
+void launch_product(const Dims& d, const T* f, const T* g, T* out, hipStream_t s);
+void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
+
+// BL derivative kernels and assembly (nsf_bl.hip)
+template <typename T>
+void launch_bl_deriv(const Dims& d, const Coef<T>& c, int axis, int order, const T* f, T* out,
+                     hipStream_t s);
+template <typename T>
+void launch_bl_assemble(const Dims& d, const Coef<T>& c, const T* q, const T* prim,
+                        const T* deriv, T* r, hipStream_t s);
+
+// untiled per-point residual kernels (nsf_naive.hip)
+template <typename T>
+void launch_ra_naive(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
+                     hipStream_t s);
+template <typename T>
+void launch_ss_grad_naive(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hipStream_t s);
+template <typename T>
+void launch_ss_naive(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
+                     T* r, hipStream_t s);
+
+// diagnostics (nsf_diag.hip); partial holds diag_partial_count(d) * NDIAG doubles
+size_t diag_partial_count(const Dims& d);
+template <typename T>
+void launch_diag(const Dims& d, const Coef<double>& c, const T* q, double* partial, double* out_dev,
+                 hipStream_t s);
+
+}  // namespace nsf

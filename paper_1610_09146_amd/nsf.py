@@ -1,0 +1,261 @@
+"""Python binding of the C ABI in ``include/nsf.h`` (``libnsf.so``).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the shared library. PyTorch supplies device memory (tensors) and
+streams; tensors are passed to the library as raw device pointers.
+
+``torch`` is imported before the library is loaded so that ``libnsf.so``
+binds to the same HIP runtime instance as torch (same ``libamdhip64.so.7``
+soname), which lets torch's streams be passed straight through.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnsf.so")
+
+OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
+BL, RA, SS, SN, RS = 0, 1, 2, 3, 4
+F64, F32 = 0, 1
+NDIAG = 16
+VARIANTS = {"BL": BL, "RA": RA, "SS": SS, "SN": SN, "RS": RS}
+PRECISIONS = {"f64": F64, "f32": F32}
+DIAG_NAMES = [
+    "ke", "enstrophy", "mean_rho", "mean_rhou", "mean_rhov", "mean_rhow", "mean_rhoE",
+    "max_rho", "max_rhou", "max_rhov", "max_rhow", "max_rhoE", "min_rho", "min_p",
+    "nonfinite", "mean_p",
+]
+
+
+class NsfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class Phys(ctypes.Structure):
+    _fields_ = [("Re", ctypes.c_double), ("Ma", ctypes.c_double), ("Pr", ctypes.c_double),
+                ("gamma", ctypes.c_double)]
+
+
+class TGV(ctypes.Structure):
+    _fields_ = [("V0", ctypes.c_double), ("pert_amp", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("pert_kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("phase", ctypes.c_double * 3)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
+                ("zchunk", ctypes.c_int32), ("fuse", ctypes.c_int32), ("naive", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libnsf.so; fails loudly if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise NsfError(EUNSUPPORTED, f"{LIB_PATH} is not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                               ctypes.c_size_t)
+        G, P, Tg, Tu = (ctypes.POINTER(Grid), ctypes.POINTER(Phys), ctypes.POINTER(TGV),
+                        ctypes.POINTER(Tuning))
+        L.nsf_status_string.restype = ctypes.c_char_p
+        L.nsf_status_string.argtypes = [ctypes.c_int]
+        L.nsf_last_error.restype = ctypes.c_char_p
+        L.nsf_version.restype = ctypes.c_int
+        L.nsf_workspace_bytes.argtypes = [G, ctypes.c_int, ctypes.c_int, Tu, ctypes.POINTER(sz)]
+        L.nsf_init_fields.argtypes = [G, P, Tg, ctypes.c_int, vp, vp, vp]
+        L.nsf_rhs.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, vp, vp, vp, sz, vp]
+        L.nsf_rk_step.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, d, i32, vp, vp, vp, vp, sz, vp]
+        L.nsf_diagnostics.argtypes = [G, P, ctypes.c_int, vp, vp, sz, ctypes.POINTER(d), vp]
+        L.nsf_device_copy.argtypes = [vp, vp, sz, vp]
+        L.nsf_timer_enable.argtypes = [ctypes.c_char_p]
+        L.nsf_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(d)]
+        L.nsf_timer_names.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> int:
+    if rc != OK:
+        L = lib()
+        raise NsfError(rc, f"{what}: {L.nsf_status_string(rc).decode()}: "
+                           f"{L.nsf_last_error().decode()}")
+    return rc
+
+
+def _grid(shape) -> Grid:
+    nx, ny, nz = (int(v) for v in shape)
+    return Grid(nx, ny, nz)
+
+
+def _phys(phys: dict) -> Phys:
+    return Phys(float(phys["Re"]), float(phys["Ma"]), float(phys["Pr"]), float(phys["gamma"]))
+
+
+def _tgv(tgv: dict | None) -> TGV:
+    tgv = tgv or {}
+    ph = tgv.get("phase", (0.0, 0.0, 0.0))
+    t = TGV(float(tgv.get("V0", 1.0)), float(tgv.get("pert_amp", 0.0)),
+            int(tgv.get("seed", 0)) & (2**64 - 1), int(tgv.get("pert_kind", 0)), 0)
+    for a in range(3):
+        t.phase[a] = float(ph[a])
+    return t
+
+
+def _tuning(tune: dict | None):
+    if not tune:
+        return None
+    t = Tuning(int(tune.get("block_x", 0)), int(tune.get("block_y", 0)), int(tune.get("zchunk", 0)),
+               int(tune.get("fuse", 0)), int(tune.get("naive", 0)))
+    return ctypes.byref(t)
+
+
+def _variant(v) -> int:
+    return VARIANTS[v] if isinstance(v, str) else int(v)
+
+
+def _precision(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise NsfError(EINVAL, "tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise NsfError(EINVAL, "tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def field_dtype(precision) -> torch.dtype:
+    return torch.float32 if _precision(precision) == F32 else torch.float64
+
+
+def version() -> int:
+    return int(lib().nsf_version())
+
+
+def workspace_bytes(shape, variant, precision, tune: dict | None = None) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().nsf_workspace_bytes(ctypes.byref(_grid(shape)), _variant(variant),
+                                     _precision(precision), _tuning(tune), ctypes.byref(out)),
+           "nsf_workspace_bytes")
+    return int(out.value)
+
+
+def init_fields(shape, phys, tgv, precision, q: torch.Tensor, q_acc: torch.Tensor | None,
+                stream=None) -> None:
+    _check(lib().nsf_init_fields(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                                 ctypes.byref(_tgv(tgv)), _precision(precision), _ptr(q),
+                                 _ptr(q_acc), _stream(stream)), "nsf_init_fields")
+
+
+def rhs(shape, phys, variant, precision, q, r, work, tune: dict | None = None, stream=None) -> None:
+    _check(lib().nsf_rhs(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)), _variant(variant),
+                         _precision(precision), _tuning(tune), _ptr(q), _ptr(r), _ptr(work),
+                         work.numel() * work.element_size(), _stream(stream)), "nsf_rhs")
+
+
+def rk_step(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, work,
+            tune: dict | None = None, stream=None) -> None:
+    _check(lib().nsf_rk_step(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                             _variant(variant), _precision(precision), _tuning(tune), float(dt),
+                             int(nsteps), _ptr(q), _ptr(q_acc), _ptr(r), _ptr(work),
+                             work.numel() * work.element_size(), _stream(stream)), "nsf_rk_step")
+
+
+def diagnostics(shape, phys, precision, q, work, stream=None, check: bool = True) -> np.ndarray:
+    out = (ctypes.c_double * NDIAG)()
+    rc = lib().nsf_diagnostics(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                               _precision(precision), _ptr(q), _ptr(work),
+                               work.numel() * work.element_size(), out, _stream(stream))
+    if check or rc != ENONFINITE:
+        _check(rc, "nsf_diagnostics")
+    return np.array(out[:], dtype=np.float64)
+
+
+def device_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None, stream=None) -> None:
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    _check(lib().nsf_device_copy(_ptr(src), _ptr(dst), n, _stream(stream)), "nsf_device_copy")
+
+
+def timer_enable(name: str | None) -> None:
+    _check(lib().nsf_timer_enable(name.encode() if name else None), "nsf_timer_enable")
+
+
+def timer_read() -> tuple[int, float]:
+    c, ms = ctypes.c_int64(0), ctypes.c_double(0.0)
+    _check(lib().nsf_timer_read(ctypes.byref(c), ctypes.byref(ms)), "nsf_timer_read")
+    return int(c.value), float(ms.value)
+
+
+def timer_names() -> list[str]:
+    return lib().nsf_timer_names().decode().split(",")
+
+
+@dataclass
+class Solver:
+    """Device buffers of one Taylor-Green run, allocated with torch.
+
+    q (precision dtype), q_acc (float64), r (precision dtype) are
+    ``[5, nz, ny, nx]`` tensors; work is a byte tensor of
+    ``workspace_bytes`` bytes.
+    """
+    shape: tuple
+    phys: dict
+    variant: int | str = RA
+    precision: int | str = F64
+    tune: dict | None = None
+    device: str = "cuda"
+    q: torch.Tensor = field(init=False)
+    q_acc: torch.Tensor = field(init=False)
+    r: torch.Tensor = field(init=False)
+    work: torch.Tensor = field(init=False)
+
+    def __post_init__(self):
+        nx, ny, nz = self.shape
+        dt = field_dtype(self.precision)
+        self.q = torch.empty((5, nz, ny, nx), dtype=dt, device=self.device)
+        self.q_acc = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=self.device)
+        self.r = torch.empty((5, nz, ny, nx), dtype=dt, device=self.device)
+        nb = workspace_bytes(self.shape, self.variant, self.precision, self.tune)
+        self.work = torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    def init(self, tgv: dict | None = None) -> None:
+        init_fields(self.shape, self.phys, tgv, self.precision, self.q, self.q_acc)
+
+    def rhs(self, q: torch.Tensor | None = None, r: torch.Tensor | None = None) -> torch.Tensor:
+        q = self.q if q is None else q
+        r = self.r if r is None else r
+        rhs(self.shape, self.phys, self.variant, self.precision, q, r, self.work, self.tune)
+        return r
+
+    def step(self, dt: float, nsteps: int = 1) -> None:
+        rk_step(self.shape, self.phys, self.variant, self.precision, dt, nsteps, self.q,
+                self.q_acc, self.r, self.work, self.tune)
+
+    def diagnostics(self, check: bool = True) -> np.ndarray:
+        return diagnostics(self.shape, self.phys, self.precision, self.q, self.work, check=check)

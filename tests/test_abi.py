@@ -1,0 +1,120 @@
+"""CPU checks of the C ABI: the built library loads, exports every function
+declared in include/nsf.h, and rejects bad arguments before touching the
+GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nsf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nsf_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def nsf():
+    from paper_1610_09146_amd import nsf as N
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1610_09146_amd import build
+        build.build()
+    return N
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("nsf_init_fields", "nsf_rhs", "nsf_rk_step", "nsf_diagnostics",
+                 "nsf_workspace_bytes"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(nsf):
+    L = nsf.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_no_undeclared_nsf_exports(nsf):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", nsf.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted({l.split()[-1] for l in out.splitlines() if " T nsf_" in l})
+    assert exported == declared_functions()
+
+
+def test_status_strings(nsf):
+    L = nsf.lib()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.nsf_status_string(code).decode().startswith("NSF_")
+    assert nsf.version() >= 100
+
+
+def test_workspace_sizes(nsf):
+    n = 32
+    npts = n ** 3
+    sizes = {v: nsf.workspace_bytes((n, n, n), v, "f64") for v in ("BL", "RA", "SS")}
+    assert sizes["RA"] >= 5 * npts * 8
+    assert sizes["SS"] - sizes["RA"] >= 9 * npts * 8
+    assert sizes["BL"] - sizes["RA"] >= 61 * npts * 8
+    s32 = nsf.workspace_bytes((n, n, n), "RA", "f32")
+    assert s32 >= 5 * npts * 4 and s32 < sizes["RA"]
+
+
+@pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024)])
+def test_bad_grid_rejected(nsf, shape):
+    with pytest.raises(nsf.NsfError) as ei:
+        nsf.workspace_bytes(shape, "RA", "f64")
+    assert ei.value.code == nsf.EINVAL
+
+
+def test_bad_variant_and_precision_rejected(nsf):
+    with pytest.raises(nsf.NsfError) as ei:
+        nsf.workspace_bytes((8, 8, 8), 9, "f64")
+    assert ei.value.code == nsf.EINVAL
+    with pytest.raises(nsf.NsfError) as ei:
+        nsf.workspace_bytes((8, 8, 8), "RA", 7)
+    assert ei.value.code == nsf.EINVAL
+
+
+def _call_rhs(nsf, shape, phys, q, r, work, nbytes, variant=1):
+    L = nsf.lib()
+    return L.nsf_rhs(ctypes.byref(nsf._grid(shape)), ctypes.byref(nsf._phys(phys)), variant, 0,
+                     None, q, r, work, nbytes, None)
+
+
+def test_rhs_validation_before_launch(nsf):
+    # fake, never-dereferenced addresses: validation must fail first
+    phys = {"Re": 1600.0, "Ma": 0.1, "Pr": 0.71, "gamma": 1.4}
+    shape = (8, 8, 8)
+    need = nsf.workspace_bytes(shape, "RA", "f64")
+    q, r, w = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000), ctypes.c_void_p(0x30000000)
+    assert _call_rhs(nsf, shape, phys, q, r, w, need - 1) == nsf.EWORKSPACE
+    assert _call_rhs(nsf, shape, phys, None, r, w, need) == nsf.EINVAL
+    assert _call_rhs(nsf, shape, dict(phys, gamma=1.0), q, r, w, need) == nsf.EINVAL
+    assert _call_rhs(nsf, shape, dict(phys, Re=-1.0), q, r, w, need) == nsf.EINVAL
+    # r overlapping q
+    assert _call_rhs(nsf, shape, phys, q, ctypes.c_void_p(0x10000008), w, need) == nsf.EINVAL
+    assert "overlap" in nsf.lib().nsf_last_error().decode()
+
+
+def test_rk_step_validation_before_launch(nsf):
+    phys = {"Re": 1600.0, "Ma": 0.1, "Pr": 0.71, "gamma": 1.4}
+    shape = (8, 8, 8)
+    need = nsf.workspace_bytes(shape, "SS", "f64")
+    L = nsf.lib()
+    args = lambda dt, n, wb: (ctypes.byref(nsf._grid(shape)), ctypes.byref(nsf._phys(phys)), 2, 0,
+                              None, dt, n, ctypes.c_void_p(0x1000000), ctypes.c_void_p(0x2000000),
+                              ctypes.c_void_p(0x3000000), ctypes.c_void_p(0x4000000), wb, None)
+    assert L.nsf_rk_step(*args(float("nan"), 1, need)) == nsf.EINVAL
+    assert L.nsf_rk_step(*args(0.01, -1, need)) == nsf.EINVAL
+    assert L.nsf_rk_step(*args(0.01, 1, need // 2)) == nsf.EWORKSPACE
+
+
+def test_timer_names(nsf):
+    names = nsf.timer_names()
+    assert "update" in names and "diag" in names
