@@ -36,6 +36,8 @@ FAMILY_BYTES = {
     "prims": (80, 40),            # q -> u, v, w, p, T
     "update": (160, 120),         # r, q_acc -> q, q_acc
     "ra_naive": (120, 60),        # q, prims -> r
+    "ra_zsweep": (120, 60),       # q, prims -> r
+    "ra_fused": (160, 120),       # q, q_acc -> q_next, q_acc
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
     "bl_deriv": (16, 8),          # one field -> one derivative
@@ -44,11 +46,16 @@ FAMILY_BYTES = {
     "diag": (40, 20),             # q -> 16 scalars
 }
 
-VARIANT_FAMILIES = {
-    "BL": ["prims", "bl_product", "bl_deriv", "bl_assemble", "update", "diag"],
-    "RA": ["prims", "ra_naive", "update", "diag"],
-    "SS": ["prims", "ss_grad_naive", "ss_naive", "update", "diag"],
-}
+def families(variant, tune):
+    if variant == "BL":
+        return ["prims", "bl_product", "bl_deriv", "bl_assemble", "update", "diag"]
+    if variant in ("RA", "SN"):
+        if tune and tune.get("fuse"):
+            return ["ra_fused", "diag"]
+        if tune and tune.get("naive"):
+            return ["prims", "ra_naive", "update", "diag"]
+        return ["prims", "ra_zsweep", "update", "diag"]
+    return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
 
 
 def log(msg: str) -> None:
@@ -66,7 +73,7 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=
     torch.cuda.synchronize()
     # warmup; also find the family with the largest summed kernel time
     fam_ms = {}
-    fams = VARIANT_FAMILIES.get(variant, [])
+    fams = families(variant, tune)
     for w in range(max(warmup, 1)):
         s.step(dt, 1)
         s.diagnostics()
@@ -96,7 +103,7 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=
     ms_per_step = (t1 - t0) * 1e3 / steps
     rate = n ** 3 * 3 * steps / (t1 - t0)
     out = {
-        "variant": variant, "precision": precision, "n": n, "steps": steps,
+        "variant": variant, "precision": precision, "n": n, "steps": steps, "tune": tune,
         "ms_per_step": ms_per_step, "pt_rhs_per_s": rate, "dominant": dominant,
         "dominant_launches": kcount, "dominant_ms_total": kms,
         "family_ms_one_step": fam_ms,
@@ -148,6 +155,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--variant", default="RA")
+    ap.add_argument("--fuse", type=int, default=1, help="fused RA stage kernel (1) or not (0)")
     ap.add_argument("--no-extras", action="store_true", help="skip BL/SS/FP32 side measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -165,18 +173,21 @@ def main() -> int:
         return 2
     nsf.lib()  # fail loudly if the HIP library is missing
     n = args.n
-    log(f"main: {args.variant} f64 n={n} steps={args.steps}")
-    main_res = run_variant(nsf, torch, W, n, args.variant, "f64", args.steps, args.warmup)
+    main_tune = {"fuse": args.fuse} if args.variant in ("RA", "SN") else None
+    log(f"main: {args.variant} {main_tune} f64 n={n} steps={args.steps}")
+    main_res = run_variant(nsf, torch, W, n, args.variant, "f64", args.steps, args.warmup,
+                           tune=main_tune)
     log(f"main done: {main_res['pt_rhs_per_s']:.3e} pt-RHS/s")
     extras = {}
     if not args.no_extras:
-        for v, prec, k in (("BL", "f64", 3), ("SS", "f64", 5), ("RA", "f32", 5)):
-            if v == args.variant and prec == "f64":
-                continue
-            log(f"extra: {v} {prec}")
-            r = run_variant(nsf, torch, W, n, v, prec, k, 1)
+        for name, v, prec, k, tune in (("BL_f64", "BL", "f64", 3, None),
+                                       ("SS_f64", "SS", "f64", 5, None),
+                                       ("RA_f64_stored_prims", "RA", "f64", 5, None),
+                                       ("RA_f32_fused", "RA", "f32", 10, {"fuse": 1})):
+            log(f"extra: {name}")
+            r = run_variant(nsf, torch, W, n, v, prec, k, 1, tune=tune)
             r["roofline"] = roofline_of(r, prec)
-            extras[f"{v}_{prec}"] = r
+            extras[name] = r
     line = {
         "metric": METRIC,
         "value": main_res["pt_rhs_per_s"],
@@ -192,7 +203,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"taylor-green {n}^3 FP64, Re=1600 Ma=0.1 Pr=0.71, "
                                f"dt={W.tgv_dt(n)}, KE+enstrophy every step",
-                   "variant": args.variant, "n": n, "dt": W.tgv_dt(n), "diag_every": 1},
+                   "variant": args.variant, "tune": main_tune, "n": n, "dt": W.tgv_dt(n),
+                   "diag_every": 1},
         "roofline": roofline_of(main_res, "f64"),
         "main": main_res,
         "extras": extras,

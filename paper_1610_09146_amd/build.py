@@ -18,7 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libnsf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["nsf_api.cpp", "nsf_pointwise.hip", "nsf_naive.hip", "nsf_bl.hip", "nsf_diag.hip"]
+SOURCES = ["nsf_api.cpp", "nsf_pointwise.hip", "nsf_naive.hip", "nsf_bl.hip", "nsf_diag.hip",
+           "nsf_zsweep.hip"]
 
 CFLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -105,9 +105,15 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t prim = 0, deriv = 0, prod = 0, diag_partial = 0, diag_out = 0, total = 0;
+    size_t prim = 0, deriv = 0, prod = 0, qb = 0, qc = 0, diag_partial = 0, diag_out = 0,
+           total = 0;
     int nderiv = 0;
+    bool fused = false;
 };
+
+bool wants_fused(int variant, const nsf_tuning* tune) {
+    return (variant == NSF_RA || variant == NSF_SN) && tune && tune->fuse && !tune->naive;
+}
 
 bool is_variant(int v) { return v >= NSF_BL && v <= NSF_RS; }
 bool is_precision(int p) { return p == NSF_F64 || p == NSF_F32; }
@@ -121,9 +127,10 @@ int deriv_arrays(int variant) {
     }
 }
 
-Layout layout_for(const Dims& d, int variant, int precision) {
+Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* tune) {
     const size_t es = precision == NSF_F32 ? 4 : 8;
     Layout L;
+    L.fused = wants_fused(variant, tune);
     size_t off = 0;
     L.prim = off;
     off = align_up(off + 5 * d.npts * es);
@@ -132,6 +139,11 @@ Layout layout_for(const Dims& d, int variant, int precision) {
     off = align_up(off + (size_t)L.nderiv * d.npts * es);
     L.prod = off;
     off = align_up(off + (variant == NSF_BL ? d.npts * es : 0));
+    // fused RA stages rotate the state through q -> qb -> qc -> q
+    L.qb = off;
+    off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
+    L.qc = off;
+    off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
     L.diag_partial = off;
     off = align_up(off + diag_partial_count(d) * NSF_NDIAG * sizeof(double));
     L.diag_out = off;
@@ -217,7 +229,8 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
         case NSF_RA:
         case NSF_SN:
             launch_prims<T>(d, c, q, prim, s);
-            launch_ra_naive<T>(d, c, q, prim, r, s);
+            if (tune && tune->naive) launch_ra_naive<T>(d, c, q, prim, r, s);
+            else launch_ra_zsweep<T>(d, c, q, prim, r, tune && tune->zchunk ? tune->zchunk : default_zchunk(d), s);
             break;
         case NSF_SS:
         case NSF_RS: {
@@ -238,6 +251,23 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
             int nsteps, T* q, double* qacc, T* r, char* work, const Layout& L, hipStream_t s) {
     static const double A[2] = {2.0 / 3.0, 5.0 / 12.0};
     static const double B[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
+    if (L.fused) {
+        const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
+        const int zc = tune->zchunk ? tune->zchunk : default_zchunk(d);
+        T* qb = (T*)(work + L.qb);
+        T* qc = (T*)(work + L.qc);
+        T* in[3] = {q, qb, qc};
+        T* out[3] = {qb, qc, q};
+        for (int step = 0; step < nsteps; ++step)
+            for (int st = 0; st < 3; ++st) {
+                StageCoef sc;
+                sc.a_dt = st < 2 ? A[st] * dt : 0.0;
+                sc.b_dt = B[st] * dt;
+                sc.last = st == 2;
+                launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, s);
+            }
+        return check_hip("rk_step launch");
+    }
     for (int step = 0; step < nsteps; ++step) {
         for (int st = 0; st < 3; ++st) {
             int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s);
@@ -284,7 +314,7 @@ int nsf_workspace_bytes(const nsf_grid* g, int variant, int precision, const nsf
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!bytes) return fail(NSF_EINVAL, "bytes is NULL");
-    *bytes = layout_for(d, variant, precision).total;
+    *bytes = layout_for(d, variant, precision, tune).total;
     return NSF_OK;
 }
 
@@ -323,7 +353,7 @@ int nsf_rhs(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!q || !r || !work) return fail(NSF_EINVAL, "q, r and work must be non-NULL");
-    const Layout L = layout_for(d, variant, precision);
+    const Layout L = layout_for(d, variant, precision, tune);
     if (work_bytes < L.total)
         return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
     const size_t fb = 5 * d.npts * (precision == NSF_F32 ? 4 : 8);
@@ -347,7 +377,7 @@ int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precis
     if (!q || !q_acc || !r || !work) return fail(NSF_EINVAL, "q, q_acc, r and work must be non-NULL");
     if (nsteps < 0) return fail(NSF_EINVAL, "nsteps %d", nsteps);
     if (!std::isfinite(dt)) return fail(NSF_EINVAL, "dt not finite");
-    const Layout L = layout_for(d, variant, precision);
+    const Layout L = layout_for(d, variant, precision, tune);
     if (work_bytes < L.total)
         return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
     const size_t fb = 5 * d.npts * (precision == NSF_F32 ? 4 : 8);
@@ -373,7 +403,7 @@ int nsf_diagnostics(const nsf_grid* g, const nsf_phys* phys, int precision, cons
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!q || !work || !out) return fail(NSF_EINVAL, "q, work and out must be non-NULL");
     // the diagnostics region is the tail of every layout; RA's is the smallest
-    const Layout L = layout_for(d, NSF_RA, precision);
+    const Layout L = layout_for(d, NSF_RA, precision, nullptr);
     if (work_bytes < L.total)
         return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
     hipStream_t s = (hipStream_t)stream;
@@ -399,7 +429,8 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 }
 
 static const char* kTimerNames =
-    "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ss_grad_naive,ss_naive,diag,copy";
+    "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ss_grad_naive,"
+    "ss_naive,diag,copy";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

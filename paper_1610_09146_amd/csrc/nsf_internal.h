@@ -66,6 +66,18 @@ template <typename T>
 void launch_ss_naive(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
                      T* r, hipStream_t s);
 
+// z-marching tiled residual kernels (nsf_zsweep.hip)
+int default_zchunk(const Dims& d);
+template <typename T>
+void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
+                      int zchunk, hipStream_t s);
+// Fused RA stage: primitives recomputed in-tile, residual, and the RK stage
+// update: qout = q_acc + A dt R (or q_acc_new on the last substep),
+// q_acc += B dt R. qout must not alias q.
+template <typename T>
+void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
+                     const StageCoef& sc, int zchunk, hipStream_t s);
+
 // diagnostics (nsf_diag.hip); partial holds diag_partial_count(d) * NDIAG doubles
 size_t diag_partial_count(const Dims& d);
 template <typename T>

@@ -1,0 +1,592 @@
+// z-marching residual kernel for the RA / SN algorithms (every derivative
+// evaluated in the residual loop, none stored; paper Section 2) on gfx950.
+//
+// A workgroup owns a TX x TY column tile of the x-y plane and marches its
+// threads up a chunk of z-planes. At output plane z:
+//   - x and y stencils read LDS: the seven fields rho, rho u_a, rho E, p, T
+//     of plane z, and u, v, w from a five-plane ring (z-2 .. z+2), each with
+//     a two-point halo (periodic wrap folded into the halo loads);
+//   - z stencils read a per-thread register queue of the seven fields at
+//     planes z-2 .. z+2 of the thread's own column, and the ring for u, v, w;
+//   - the cross derivatives with z are taken as D_z of in-plane derivatives
+//     (D_z D_x u, D_z D_y v, D_z D_x w, D_z D_y w: mixed central differences
+//     commute), the in-plane derivatives being formed at the leading plane
+//     z+2 and queued, so no thread needs a z-halo column;
+//   - D_x D_y v and D_y D_x u use the LDS corner halo.
+// Terms are folded into running sums direction by direction to keep few
+// values live. FUSED = true recomputes the primitives from q inside the tile
+// (no primitive arrays) and applies the low-storage RK stage update in the
+// epilogue, writing the next stage's state to a different buffer.
+#include "nsf_internal.h"
+
+namespace nsf {
+
+namespace {
+
+constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
+
+__device__ __forceinline__ int pmod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+// Give every XCD a contiguous range of tiles so that neighbouring tiles
+// (which share halos) run under the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int per = nb / kXCD, extra = nb % kXCD;
+    const int x = bid % kXCD, k = bid / kXCD;
+    return x * per + (x < extra ? x : extra) + k;
+}
+
+template <int TX, int TY>
+struct Geom {
+    static constexpr int LX = TX + 4, LY = TY + 4;
+    static constexpr int NT = TX * TY;
+    static constexpr int NPL = LX * LY;
+    static constexpr int NHALO = NPL - NT;
+    static constexpr int HPT = (NHALO + NT - 1) / NT;
+};
+
+// Halo position h (0 .. NHALO-1) -> LDS coordinates: two full rows below,
+// two above, then the two-column strips left and right of the tile rows.
+template <int TX, int TY>
+__device__ __forceinline__ void halo_pos(int h, int& hx, int& hy) {
+    constexpr int LX = TX + 4;
+    constexpr int ROWS2 = 2 * LX;
+    if (h < ROWS2) {
+        hy = h / LX;
+        hx = h % LX;
+    } else if (h < 2 * ROWS2) {
+        const int t = h - ROWS2;
+        hy = TY + 2 + t / LX;
+        hx = t % LX;
+    } else {
+        const int t = h - 2 * ROWS2;
+        hy = 2 + t / 4;
+        const int c = t % 4;
+        hx = c < 2 ? c : TX + c;
+    }
+}
+
+// Own-column values queued in registers (the velocity lives in the LDS ring).
+template <typename T>
+struct Pt {
+    T rho, m0, m1, m2, E, p, t;
+};
+
+// Raw loads of one point: q (and, when primitives are stored, prim).
+template <typename T, bool FUSED>
+struct Raw {
+    T q[5];
+    T pr[FUSED ? 1 : 5];
+};
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void load_raw(Raw<T, FUSED>& r, const T* __restrict__ q,
+                                         const T* __restrict__ prim, size_t n, size_t off) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r.q[f] = q[f * n + off];
+    if (!FUSED) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) r.pr[f] = prim[f * n + off];
+    }
+}
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ Pt<T> finish(const Raw<T, FUSED>& r, const Coef<T>& k, T uvw[3]) {
+    Pt<T> P;
+    P.rho = r.q[0];
+    P.m0 = r.q[1];
+    P.m1 = r.q[2];
+    P.m2 = r.q[3];
+    P.E = r.q[4];
+    if (FUSED) {
+        const Prim<T> pv = primitives(r.q[0], r.q[1], r.q[2], r.q[3], r.q[4], k);
+        uvw[0] = pv.u;
+        uvw[1] = pv.v;
+        uvw[2] = pv.w;
+        P.p = pv.p;
+        P.t = pv.t;
+    } else {
+        uvw[0] = r.pr[0];
+        uvw[1] = r.pr[1];
+        uvw[2] = r.pr[2];
+        P.p = r.pr[3];
+        P.t = r.pr[4];
+    }
+    return P;
+}
+
+// Halo loads for the u, v, w ring plane (velocity only).
+template <typename T, bool FUSED>
+struct RawV {
+    T a[FUSED ? 4 : 3];
+};
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void load_rawv(RawV<T, FUSED>& r, const T* __restrict__ q,
+                                          const T* __restrict__ prim, size_t n, size_t off) {
+    if (FUSED) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) r.a[f] = q[f * n + off];
+    } else {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) r.a[f] = prim[f * n + off];
+    }
+}
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void finish_v(const RawV<T, FUSED>& r, T& u, T& v, T& w) {
+    if (FUSED) {
+        const T ir = fast_rcp(r.a[0]);
+        u = r.a[1] * ir;
+        v = r.a[2] * ir;
+        w = r.a[3] * ir;
+    } else {
+        u = r.a[0];
+        v = r.a[1];
+        w = r.a[2];
+    }
+}
+
+// Halo loads for the seven-field plane (rho, m, E, p, T).
+template <typename T, bool FUSED>
+struct RawP {
+    T a[FUSED ? 5 : 7];
+};
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void load_rawp(RawP<T, FUSED>& r, const T* __restrict__ q,
+                                          const T* __restrict__ prim, size_t n, size_t off) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) r.a[f] = q[f * n + off];
+    if (!FUSED) {
+        r.a[5] = prim[3 * n + off];
+        r.a[6] = prim[4 * n + off];
+    }
+}
+
+template <typename T, bool FUSED>
+__device__ __forceinline__ void finish_p(const RawP<T, FUSED>& r, const Coef<T>& k, T out[7]) {
+#pragma unroll
+    for (int f = 0; f < 5; ++f) out[f] = r.a[f];
+    if (FUSED) {
+        const Prim<T> pv = primitives(r.a[0], r.a[1], r.a[2], r.a[3], r.a[4], k);
+        out[5] = pv.p;
+        out[6] = pv.t;
+    } else {
+        out[5] = r.a[5];
+        out[6] = r.a[6];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T a1, T a2) {
+    return a1 * (p1 - m1) + a2 * (p2 - m2);
+}
+
+template <typename T>
+__device__ __forceinline__ T D2(T m2, T m1, T c, T p1, T p2, T b0, T b1, T b2) {
+    return b0 * c + b1 * (p1 + m1) + b2 * (p2 + m2);
+}
+
+}  // namespace
+
+template <typename T>
+struct ZArgs {
+    Dims d;
+    Coef<T> k;
+    const T* q;
+    const T* prim;
+    T* r;
+    T* qout;
+    double* qacc;
+    double a_dt, b_dt;
+    int last;
+    int zchunk, tiles_x, tiles_y;
+};
+
+namespace {
+
+// Running sums of the residual (paper Section 2, residual assembly), folded
+// one direction at a time.
+template <typename T>
+struct Acc {
+    T S0;      // sum_b D_b(rho u_b) + u_b D_b rho
+    T Sm[3];   // sum_b D_b(rho u_a u_b) + u_b D_b(rho u_a)
+    T SE;      // sum_b D_b(rho E u_b) + u_b D_b(rho E)
+    T PF;      // sum_b D_b(p u_b)
+    T HEAT;    // sum_b D2_b T
+    T LAP[3];  // sum_b D2_b u_a
+    T D2aa[3]; // D2_a u_a
+    T Dp[3];   // D_a p
+    T G[3][3]; // G_ab = D_b u_a
+};
+
+// Fold direction B given stencil values (index 0..4 = offsets -2..2) of the
+// ten fields along that direction. rho/m/E/p/T arrays: f[field][5];
+// ub = velocity component B along the stencil.
+template <typename T, int B>
+__device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3][5], const T E[5],
+                                         const T p[5], const T tt[5], const T vel[3][5], T a1,
+                                         T a2, T b0, T b1, T b2, const T uc[3]) {
+    const T* ub = vel[B];
+    const T Drho = D1(rho[0], rho[1], rho[3], rho[4], a1, a2);
+    A.S0 += D1(m[B][0], m[B][1], m[B][3], m[B][4], a1, a2) + uc[B] * Drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const T Dm = D1(m[a][0], m[a][1], m[a][3], m[a][4], a1, a2);
+        const T Dmu = D1(m[a][0] * ub[0], m[a][1] * ub[1], m[a][3] * ub[3], m[a][4] * ub[4], a1, a2);
+        A.Sm[a] += Dmu + uc[B] * Dm;
+        A.G[a][B] = D1(vel[a][0], vel[a][1], vel[a][3], vel[a][4], a1, a2);
+        const T d2 = D2(vel[a][0], vel[a][1], vel[a][2], vel[a][3], vel[a][4], b0, b1, b2);
+        A.LAP[a] += d2;
+        if (a == B) A.D2aa[a] = d2;
+    }
+    const T DE = D1(E[0], E[1], E[3], E[4], a1, a2);
+    const T DEu = D1(E[0] * ub[0], E[1] * ub[1], E[3] * ub[3], E[4] * ub[4], a1, a2);
+    A.SE += DEu + uc[B] * DE;
+    A.PF += D1(p[0] * ub[0], p[1] * ub[1], p[3] * ub[3], p[4] * ub[4], a1, a2);
+    A.Dp[B] = D1(p[0], p[1], p[3], p[4], a1, a2);
+    A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
+}
+
+template <typename T>
+__device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rho, const T m[3],
+                                         T E, const T u[3], const Coef<T>& k, T R[5]) {
+    const T div = A.G[0][0] + A.G[1][1] + A.G[2][2];
+    R[0] = T(-0.5) * (A.S0 + rho * div);
+    T V[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        V[a] = k.inv_Re * (A.LAP[a] + k.third * (A.D2aa[a] + cross[a]));
+        R[1 + a] = T(-0.5) * (A.Sm[a] + m[a] * div) - A.Dp[a] + V[a];
+    }
+    T gg = T(0), gt = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            gg += A.G[a][b] * A.G[a][b];
+            gt += A.G[a][b] * A.G[b][a];
+        }
+    const T work = k.inv_Re * (gg + gt - k.two_thirds * div * div);
+    R[4] = T(-0.5) * (A.SE + E * div) - A.PF + k.kappa * A.HEAT + work +
+           (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
+}
+
+template <typename T, int TX, int TY, bool FUSED>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
+                               amdgpu_waves_per_eu(2, 2)))
+k_ra_zsweep(ZArgs<T> A) {
+    using G = Geom<TX, TY>;
+    constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
+    constexpr int RING = 5;
+    __shared__ T sP[7 * NPL];         // rho, m0, m1, m2, E, p, T of plane z
+    __shared__ T sV[RING * 3 * NPL];  // ring slot (plane mod 5) x {u, v, w}
+
+    const Dims d = A.d;
+    const Coef<T> k = A.k;
+    const size_t n = d.npts;
+    const size_t plane = (size_t)d.nx * d.ny;
+
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tix = t % A.tiles_x;
+    const int tiy = (t / A.tiles_x) % A.tiles_y;
+    const int tiz = t / (A.tiles_x * A.tiles_y);
+    const int x0 = tix * TX, y0 = tiy * TY, z0 = tiz * A.zchunk;
+    const int z1 = min(z0 + A.zchunk, d.nz);
+
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int gi = x0 + lx, gj = y0 + ly;
+    const bool active = gi < d.nx && gj < d.ny;
+    const size_t col = (size_t)pmod(gj, d.ny) * d.nx + pmod(gi, d.nx);
+    const int own = (ly + 2) * LX + (lx + 2);
+
+    int hidx[HPT];
+    size_t hcol[HPT];
+    bool hval[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) {
+        const int hh = tid + h * NT;
+        hval[h] = hh < NHALO;
+        int hx = 0, hy = 0;
+        if (hval[h]) halo_pos<TX, TY>(hh, hx, hy);
+        hidx[h] = hy * LX + hx;
+        hcol[h] = (size_t)pmod(y0 + hy - 2, d.ny) * d.nx + pmod(x0 + hx - 2, d.nx);
+    }
+    auto poff = [&](int z) { return (size_t)pmod(z, d.nz) * plane; };
+    auto ring = [&](int z) { return sV + pmod(z, RING) * 3 * NPL; };
+
+    // register queue of the own column, planes z-2 .. z+2 (velocity in the ring)
+    Pt<T> Qz[5];
+    T uvw[5][3];
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        Raw<T, FUSED> raw;
+        load_raw<T, FUSED>(raw, A.q, A.prim, n, poff(z0 - 2 + s) + col);
+        Qz[s] = finish<T, FUSED>(raw, k, uvw[s]);
+    }
+    T unew[3] = {uvw[4][0], uvw[4][1], uvw[4][2]};  // own velocity of plane z+2
+
+    // queued in-plane derivatives for the z cross terms: Dx u + Dy v, Dx w, Dy w
+    T Xs[5], Xw[5], Yw[5];
+    auto leading = [&](const T* V, T& s, T& xw, T& yw) {
+        const T* U = V;
+        const T* Vv = V + NPL;
+        const T* W = V + 2 * NPL;
+        const T dxu = D1(U[own - 2], U[own - 1], U[own + 1], U[own + 2], k.a1[0], k.a2[0]);
+        const T dyv = D1(Vv[own - 2 * LX], Vv[own - LX], Vv[own + LX], Vv[own + 2 * LX], k.a1[1], k.a2[1]);
+        s = dxu + dyv;
+        xw = D1(W[own - 2], W[own - 1], W[own + 1], W[own + 2], k.a1[0], k.a2[0]);
+        yw = D1(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX], k.a1[1], k.a2[1]);
+    };
+
+    // preamble: ring planes z0-2 .. z0+1 and their queued in-plane derivatives
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int zz = z0 - 2 + s;
+        T* V = ring(zz);
+        V[own] = uvw[s][0];
+        V[NPL + own] = uvw[s][1];
+        V[2 * NPL + own] = uvw[s][2];
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+            if (hval[h]) {
+                RawV<T, FUSED> rv;
+                load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
+                T u, v, w;
+                finish_v<T, FUSED>(rv, u, v, w);
+                V[hidx[h]] = u;
+                V[NPL + hidx[h]] = v;
+                V[2 * NPL + hidx[h]] = w;
+            }
+        __syncthreads();
+        leading(V, Xs[s], Xw[s], Yw[s]);
+    }
+
+    // prefetched halo values for the first iteration
+    RawV<T, FUSED> hv[HPT];
+    RawP<T, FUSED> hp[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h)
+        if (hval[h]) {
+            load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+            load_rawp<T, FUSED>(hp[h], A.q, A.prim, n, poff(z0) + hcol[h]);
+        }
+
+    for (int z = z0; z < z1; ++z) {
+        // (a) LDS: ring slot of plane z+2 (velocity) and the plane-z fields;
+        // the slot of plane z+2 last held plane z-3, whose readers finished
+        // before the barrier that ended the previous iteration
+        T* Vl = ring(z + 2);
+        Vl[own] = unew[0];
+        Vl[NPL + own] = unew[1];
+        Vl[2 * NPL + own] = unew[2];
+        sP[own] = Qz[2].rho;
+        sP[NPL + own] = Qz[2].m0;
+        sP[2 * NPL + own] = Qz[2].m1;
+        sP[3 * NPL + own] = Qz[2].m2;
+        sP[4 * NPL + own] = Qz[2].E;
+        sP[5 * NPL + own] = Qz[2].p;
+        sP[6 * NPL + own] = Qz[2].t;
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+            if (hval[h]) {
+                T u, v, w;
+                finish_v<T, FUSED>(hv[h], u, v, w);
+                Vl[hidx[h]] = u;
+                Vl[NPL + hidx[h]] = v;
+                Vl[2 * NPL + hidx[h]] = w;
+                T f7[7];
+                finish_p<T, FUSED>(hp[h], k, f7);
+#pragma unroll
+                for (int f = 0; f < 7; ++f) sP[f * NPL + hidx[h]] = f7[f];
+            }
+        // (b) prefetch the next iteration's loads
+        Raw<T, FUSED> nxt;
+        load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+#pragma unroll
+        for (int h = 0; h < HPT; ++h)
+            if (hval[h]) {
+                load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                load_rawp<T, FUSED>(hp[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+            }
+        __syncthreads();
+
+        // (c) leading-plane in-plane derivatives for the z cross terms
+        leading(Vl, Xs[4], Xw[4], Yw[4]);
+
+        // (d) residual at plane z
+        const T* Vc = ring(z);
+        Acc<T> ac;
+        ac.S0 = ac.SE = ac.PF = ac.HEAT = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ac.Sm[a] = ac.LAP[a] = T(0);
+        const T uc[3] = {Vc[own], Vc[NPL + own], Vc[2 * NPL + own]};
+        {  // x
+            T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const int o = own + s - 2;
+                rho[s] = sP[o];
+                m[0][s] = sP[NPL + o];
+                m[1][s] = sP[2 * NPL + o];
+                m[2][s] = sP[3 * NPL + o];
+                E[s] = sP[4 * NPL + o];
+                p[s] = sP[5 * NPL + o];
+                tt[s] = sP[6 * NPL + o];
+                vel[0][s] = Vc[o];
+                vel[1][s] = Vc[NPL + o];
+                vel[2][s] = Vc[2 * NPL + o];
+            }
+            fold_dir<T, 0>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
+        }
+        {  // y
+            T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const int o = own + (s - 2) * LX;
+                rho[s] = sP[o];
+                m[0][s] = sP[NPL + o];
+                m[1][s] = sP[2 * NPL + o];
+                m[2][s] = sP[3 * NPL + o];
+                E[s] = sP[4 * NPL + o];
+                p[s] = sP[5 * NPL + o];
+                tt[s] = sP[6 * NPL + o];
+                vel[0][s] = Vc[o];
+                vel[1][s] = Vc[NPL + o];
+                vel[2][s] = Vc[2 * NPL + o];
+            }
+            fold_dir<T, 1>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
+        }
+        {  // z: register queue, velocity from the ring
+            T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const T* Vs = ring(z - 2 + s);
+                rho[s] = Qz[s].rho;
+                m[0][s] = Qz[s].m0;
+                m[1][s] = Qz[s].m1;
+                m[2][s] = Qz[s].m2;
+                E[s] = Qz[s].E;
+                p[s] = Qz[s].p;
+                tt[s] = Qz[s].t;
+                vel[0][s] = Vs[own];
+                vel[1][s] = Vs[NPL + own];
+                vel[2][s] = Vs[2 * NPL + own];
+            }
+            fold_dir<T, 2>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
+        }
+        // cross derivatives sum_{c != a} D_a(G_cc)
+        T cross[3];
+        {
+            const T* U = Vc;
+            const T* Vv = Vc + NPL;
+            auto dyv = [&](int mx) {
+                const int o = own + mx;
+                return D1(Vv[o - 2 * LX], Vv[o - LX], Vv[o + LX], Vv[o + 2 * LX], k.a1[1], k.a2[1]);
+            };
+            auto dxu = [&](int my) {
+                const int o = own + my * LX;
+                return D1(U[o - 2], U[o - 1], U[o + 1], U[o + 2], k.a1[0], k.a2[0]);
+            };
+            const T dxdyv = D1(dyv(-2), dyv(-1), dyv(1), dyv(2), k.a1[0], k.a2[0]);
+            const T dydxu = D1(dxu(-2), dxu(-1), dxu(1), dxu(2), k.a1[1], k.a2[1]);
+            const T a1z = k.a1[2], a2z = k.a2[2];
+            cross[0] = dxdyv + D1(Xw[0], Xw[1], Xw[3], Xw[4], a1z, a2z);
+            cross[1] = dydxu + D1(Yw[0], Yw[1], Yw[3], Yw[4], a1z, a2z);
+            cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], a1z, a2z);
+        }
+        T R[5];
+        {
+            const T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
+            finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R);
+        }
+        const size_t oidx = (size_t)z * plane + col;
+        if (active) {
+            if (FUSED) {
+                double acc[5];
+#pragma unroll
+                for (int f = 0; f < 5; ++f) acc[f] = A.qacc[f * n + oidx];
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    const double rr = (double)R[f];
+                    const double na = fma(A.b_dt, rr, acc[f]);
+                    A.qacc[f * n + oidx] = na;
+                    A.qout[f * n + oidx] = A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]);
+                }
+            } else {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) A.r[f * n + oidx] = R[f];
+            }
+        }
+        __syncthreads();
+        // (e) rotate the queues
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            Qz[s] = Qz[s + 1];
+            Xs[s] = Xs[s + 1];
+            Xw[s] = Xw[s + 1];
+            Yw[s] = Yw[s + 1];
+        }
+        Qz[4] = finish<T, FUSED>(nxt, k, unew);
+    }
+}
+
+template <typename T, int TX, int TY, bool FUSED>
+void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
+    ZArgs<T> a = a0;
+    const Dims& d = a.d;
+    a.zchunk = zchunk < 1 ? d.nz : (zchunk > d.nz ? d.nz : zchunk);
+    a.tiles_x = (d.nx + TX - 1) / TX;
+    a.tiles_y = (d.ny + TY - 1) / TY;
+    const int tiles_z = (d.nz + a.zchunk - 1) / a.zchunk;
+    const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * tiles_z);
+    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED>), dim3(nb), dim3(TX * TY), 0, s, a);
+}
+
+}  // namespace
+
+int default_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 32 : d.nz); }
+
+template <typename T>
+void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
+                      int zchunk, hipStream_t s) {
+    TimerScope ts("ra_zsweep", s);
+    ZArgs<T> a{};
+    a.d = d;
+    a.k = c;
+    a.q = q;
+    a.prim = prim;
+    a.r = r;
+    launch_tiles<T, 32, 8, false>(a, zchunk, s);
+}
+
+template <typename T>
+void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
+                     const StageCoef& sc, int zchunk, hipStream_t s) {
+    TimerScope ts("ra_fused", s);
+    ZArgs<T> a{};
+    a.d = d;
+    a.k = c;
+    a.q = q;
+    a.qout = qout;
+    a.qacc = qacc;
+    a.a_dt = sc.a_dt;
+    a.b_dt = sc.b_dt;
+    a.last = sc.last;
+    launch_tiles<T, 32, 8, true>(a, zchunk, s);
+}
+
+#define NSF_INST(T)                                                                          \
+    template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
+                                      int, hipStream_t);                                    \
+    template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
+                                     const StageCoef&, int, hipStream_t);
+NSF_INST(float)
+NSF_INST(double)
+#undef NSF_INST
+
+}  // namespace nsf
