@@ -115,6 +115,61 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=
     return out
 
 
+def run_batch(nsf, torch, W, precision, steps, warmup=1):
+    """64 uneven Taylor-Green instances, each step one graph replay (three
+    persistent stage launches)."""
+    insts = W.batch_instances()
+    b = nsf.Batch(insts, precision)
+    pts = b.points()
+    for _ in range(warmup):
+        b.step(1)
+    nsf.timer_enable("batch_step")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c, ms = nsf.timer_read()
+    nsf.timer_enable(None)
+    d = b.diagnostics()
+    nitems, nblocks = b.info()
+    per_pt = FAMILY_BYTES["ra_fused"][0 if precision == "f64" else 1] * 3
+    avg_s = ms / max(c, 1) / 1e3
+    out = {
+        "instances": len(insts), "points": pts, "precision": precision, "steps": steps,
+        "ms_per_step": (t1 - t0) * 1e3 / steps,
+        "pt_rhs_per_s": pts * 3 * steps / (t1 - t0),
+        "work_items": nitems, "persistent_blocks": nblocks,
+        "roofline": {"bound": "hbm", "kernel": "ra_batch (3 stage launches per graph replay)",
+                     "achieved": round(per_pt * pts / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(per_pt * pts / avg_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_graph_ms": round(avg_s * 1e3, 4)},
+        "ke_min_max": [float(d[:, 0].min()), float(d[:, 0].max())],
+    }
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    # the same ensemble advanced by the plain single-grid FP64/FP32 path, one
+    # instance after another (fused RA, one rk_step call per instance)
+    solvers = []
+    for inst in insts:
+        sv = nsf.Solver(inst["shape"], inst["phys"], "RA", precision, tune={"fuse": 1})
+        sv.init(inst["tgv"])
+        sv.step(inst["dt"], 1)
+        solvers.append(sv)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for sv, inst in zip(solvers, insts):
+            sv.step(inst["dt"], 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out["sequential_single_pt_rhs_per_s"] = pts * 3 * steps / (t1 - t0)
+    del solvers
+    torch.cuda.empty_cache()
+    return out
+
+
 def roofline_of(res, precision):
     fam = res["dominant"]
     if not fam or res["dominant_launches"] == 0:
@@ -158,6 +213,8 @@ def main() -> int:
     ap.add_argument("--fuse", type=int, default=1, help="fused RA stage kernel (1) or not (0)")
     ap.add_argument("--no-extras", action="store_true", help="skip BL/SS/FP32 side measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -172,6 +229,14 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     nsf.lib()  # fail loudly if the HIP library is missing
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            nsf.device_copy(src, dst)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB")
+        del src, dst
     n = args.n
     main_tune = {"fuse": args.fuse} if args.variant in ("RA", "SN") else None
     log(f"main: {args.variant} {main_tune} f64 n={n} steps={args.steps}")
@@ -188,6 +253,9 @@ def main() -> int:
             r = run_variant(nsf, torch, W, n, v, prec, k, 1, tune=tune)
             r["roofline"] = roofline_of(r, prec)
             extras[name] = r
+        for prec in ("f64", "f32"):
+            log(f"extra: batch64 {prec}")
+            extras[f"batch64_{prec}"] = run_batch(nsf, torch, W, prec, 10)
     line = {
         "metric": METRIC,
         "value": main_res["pt_rhs_per_s"],

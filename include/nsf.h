@@ -160,6 +160,43 @@ int nsf_diagnostics(const nsf_grid *g, const nsf_phys *phys, int precision,
                     const void *q, void *work, size_t work_bytes, double *out,
                     void *stream);
 
+/* ---------------------------------------------------------------- batched form
+ * Many independent Taylor-Green-type instances (own grid, parameters, dt)
+ * advance together with the fused recompute-all stage: one persistent
+ * launch per RK stage walks a work list of (instance, tile) items across all
+ * instances, and the three stage launches of a step are captured once in a
+ * hipGraph. Each instance's q (precision dtype) and q_acc (double) are
+ * caller-owned device buffers with the single-grid contract of nsf_rk_step;
+ * `work` (nsf_batch_workspace_bytes) holds the other two stage states and
+ * the diagnostics scratch of every instance and must stay allocated until
+ * nsf_batch_destroy. The handle owns only the graph, a private capture
+ * stream and the small device work list it allocates. */
+typedef struct nsf_batch nsf_batch;
+
+int nsf_batch_workspace_bytes(int32_t count, const nsf_grid *grids, int precision, size_t *bytes);
+
+/* Build the work list and capture one step. grids, phys, dt, q, q_acc are
+ * host arrays of `count` entries. Synchronous (allocates and uploads). */
+int nsf_batch_create(int32_t count, const nsf_grid *grids, const nsf_phys *phys, const double *dt,
+                     int precision, void *const *q, double *const *q_acc, void *work,
+                     size_t work_bytes, void *stream, nsf_batch **out);
+
+/* Advance every instance nsteps steps by replaying the captured graph on
+ * `stream`. Asynchronous. */
+int nsf_batch_step(nsf_batch *b, int32_t nsteps, void *stream);
+
+/* The same stage launches issued directly (no graph); same results. */
+int nsf_batch_step_eager(nsf_batch *b, int32_t nsteps, void *stream);
+
+/* Diagnostics (as nsf_diagnostics) of every instance into out[count][NSF_NDIAG]
+ * (host memory). Waits for the stream. */
+int nsf_batch_diagnostics(nsf_batch *b, double *out, void *stream);
+
+/* Work-list size and persistent grid size of the stage launches. */
+int nsf_batch_info(const nsf_batch *b, int32_t *nitems, int32_t *nblocks);
+
+int nsf_batch_destroy(nsf_batch *b);
+
 /* Device-to-device copy of `bytes` with a plain streaming kernel; used to
  * calibrate achievable HBM bandwidth and the memory counters. */
 int nsf_device_copy(const void *src, void *dst, size_t bytes, void *stream);

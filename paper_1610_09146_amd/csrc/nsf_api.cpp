@@ -32,6 +32,14 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+int set_error(int code, const char* msg) {
+    g_err = msg ? msg : "";
+    return code;
+}
+
+namespace {
 int check_hip(const char* where) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(NSF_EHIP, "%s: %s", where, hipGetErrorString(e));
@@ -57,6 +65,8 @@ TimerScope::TimerScope(const char* family, hipStream_t s) : on(false), stream(s)
     Timer& t = timer();
     std::lock_guard<std::mutex> lk(t.mu);
     if (t.family.empty() || t.family != family) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     if (t.used == t.ev.size()) {
         hipEvent_t a, b;
         if (hipEventCreate(&a) != hipSuccess) return;
@@ -430,7 +440,7 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ss_grad_naive,"
-    "ss_naive,diag,copy";
+    "ss_naive,diag,copy,ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

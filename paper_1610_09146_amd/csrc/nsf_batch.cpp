@@ -1,0 +1,244 @@
+// Batched form: many independent Taylor-Green-type instances of uneven grid
+// sizes and parameters advance together, one persistent launch per RK stage
+// over a work list of (instance, tile) items, the three stage launches of a
+// step captured once in a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/nsf.h"
+#include "nsf_internal.h"
+
+using namespace nsf;
+
+struct nsf_batch {
+    int count = 0;
+    int precision = NSF_F64;
+    int nitems = 0;
+    int nblocks = 0;
+    std::vector<Dims> dims;
+    std::vector<nsf_phys> phys;
+    std::vector<void*> q;
+    std::vector<double*> diag_partial;
+    double* diag_out = nullptr;  // count * NSF_NDIAG doubles inside `work`
+    void* desc_dev = nullptr;
+    int2* items_dev = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int bfail(int code, const char* msg) { return set_error(code, msg); }
+
+// Per-instance work: the two extra stage states (qb, qc) and the
+// diagnostics partials; then count * NDIAG doubles of reduced output.
+size_t instance_bytes(const Dims& d, int precision) {
+    const size_t es = precision == NSF_F32 ? 4 : 8;
+    return 2 * align_up(5 * d.npts * es) + align_up(diag_partial_count(d) * NSF_NDIAG * sizeof(double));
+}
+
+int check_grids(int32_t count, const nsf_grid* grids, std::vector<Dims>& dims) {
+    if (count < 1 || !grids) return bfail(NSF_EINVAL, "batch: count < 1 or grids NULL");
+    dims.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const nsf_grid& g = grids[i];
+        if (g.nx < 5 || g.ny < 5 || g.nz < 5) return bfail(NSF_EINVAL, "batch: every axis needs >= 5 points");
+        const size_t n = (size_t)g.nx * g.ny * g.nz;
+        if (n > (size_t)1 << 31) return bfail(NSF_EINVAL, "batch: instance too large");
+        dims[i] = Dims{g.nx, g.ny, g.nz, n};
+    }
+    return NSF_OK;
+}
+
+template <typename T>
+int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* phys,
+                 const double* dt, void* const* q, double* const* qacc, char* work) {
+    std::vector<BatchDesc<T>> desc(b->count);
+    std::vector<int2> items;
+    size_t off = 0;
+    const size_t es = sizeof(T);
+    for (int i = 0; i < b->count; ++i) {
+        const Dims& d = dims[i];
+        BatchDesc<T>& bd = desc[i];
+        bd.d = d;
+        bd.k = make_coef<T>(d, phys[i].Re, phys[i].Ma, phys[i].Pr, phys[i].gamma);
+        bd.q = (T*)q[i];
+        bd.qb = (T*)(work + off);
+        off += align_up(5 * d.npts * es);
+        bd.qc = (T*)(work + off);
+        off += align_up(5 * d.npts * es);
+        b->diag_partial[i] = (double*)(work + off);
+        off += align_up(diag_partial_count(d) * NSF_NDIAG * sizeof(double));
+        bd.qacc = qacc[i];
+        bd.dt = dt[i];
+        int tx, ty, tz, zc;
+        tile_counts(d, default_zchunk(d), &tx, &ty, &tz, &zc);
+        bd.zchunk = zc;
+        bd.tiles_x = tx;
+        bd.tiles_y = ty;
+        bd.tiles = tx * ty * tz;
+        for (int t = 0; t < bd.tiles; ++t) items.push_back(int2{i, t});
+    }
+    b->diag_out = (double*)(work + off);
+    b->nitems = (int)items.size();
+    hipError_t e = hipMalloc(&b->desc_dev, desc.size() * sizeof(BatchDesc<T>));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->items_dev, items.size() * sizeof(int2));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->desc_dev, desc.data(), desc.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
+    return NSF_OK;
+}
+
+template <typename T>
+void enqueue_step(nsf_batch* b, hipStream_t s) {
+    for (int st = 0; st < 3; ++st)
+        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->nitems, st, b->nblocks, s);
+}
+
+void release(nsf_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->desc_dev) (void)hipFree(b->desc_dev);
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsf_batch_workspace_bytes(int32_t count, const nsf_grid* grids, int precision, size_t* bytes) {
+    std::vector<Dims> dims;
+    int rc = check_grids(count, grids, dims);
+    if (rc) return rc;
+    if (precision != NSF_F64 && precision != NSF_F32) return bfail(NSF_EINVAL, "batch: precision");
+    if (!bytes) return bfail(NSF_EINVAL, "batch: bytes NULL");
+    size_t total = 0;
+    for (const Dims& d : dims) total += instance_bytes(d, precision);
+    *bytes = total + align_up((size_t)count * NSF_NDIAG * sizeof(double));
+    return NSF_OK;
+}
+
+int nsf_batch_create(int32_t count, const nsf_grid* grids, const nsf_phys* phys, const double* dt,
+                     int precision, void* const* q, double* const* q_acc, void* work,
+                     size_t work_bytes, void* stream, nsf_batch** out) {
+    (void)stream;
+    if (!out) return bfail(NSF_EINVAL, "batch: out NULL");
+    *out = nullptr;
+    std::vector<Dims> dims;
+    int rc = check_grids(count, grids, dims);
+    if (rc) return rc;
+    if (!phys || !dt || !q || !q_acc || !work) return bfail(NSF_EINVAL, "batch: NULL argument");
+    if (precision != NSF_F64 && precision != NSF_F32) return bfail(NSF_EINVAL, "batch: precision");
+    for (int i = 0; i < count; ++i) {
+        const nsf_phys& p = phys[i];
+        if (!(p.Re > 0) || !(p.Ma > 0) || !(p.Pr > 0) || !(p.gamma > 1) || !std::isfinite(dt[i]))
+            return bfail(NSF_EINVAL, "batch: bad phys or dt");
+        if (!q[i] || !q_acc[i]) return bfail(NSF_EINVAL, "batch: NULL state pointer");
+    }
+    size_t need = 0;
+    if ((rc = nsf_batch_workspace_bytes(count, grids, precision, &need))) return rc;
+    if (work_bytes < need) return bfail(NSF_EWORKSPACE, "batch: work buffer too small");
+
+    nsf_batch* b = new nsf_batch();
+    b->count = count;
+    b->precision = precision;
+    b->dims = dims;
+    b->phys.assign(phys, phys + count);
+    b->q.assign(q, q + count);
+    b->diag_partial.resize(count);
+    rc = precision == NSF_F64
+             ? build_tables<double>(b, dims, phys, dt, q, q_acc, (char*)work)
+             : build_tables<float>(b, dims, phys, dt, q, q_acc, (char*)work);
+    if (rc) { release(b); return rc; }
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = precision == NSF_F64 ? batch_blocks_per_cu<double>() : batch_blocks_per_cu<float>();
+    if (e != hipSuccess || cus < 1 || per_cu < 1) { release(b); return bfail(NSF_EHIP, "batch: occupancy query failed"); }
+    b->nblocks = (cus * per_cu) / 8 * 8;  // a multiple of the XCD count
+    if (b->nblocks < 8) b->nblocks = 8;
+
+    // capture one step (three stage launches) into a graph on a private stream
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        if (precision == NSF_F64) enqueue_step<double>(b, b->cap);
+        else enqueue_step<float>(b, b->cap);
+        e = hipStreamEndCapture(b->cap, &b->graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { release(b); return bfail(NSF_EHIP, hipGetErrorString(e)); }
+    *out = b;
+    return NSF_OK;
+}
+
+int nsf_batch_step(nsf_batch* b, int32_t nsteps, void* stream) {
+    if (!b || nsteps < 0) return bfail(NSF_EINVAL, "batch_step: bad handle or nsteps");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < nsteps; ++i) {
+        TimerScope ts("batch_step", s);  // one record per replayed step
+        hipError_t e = hipGraphLaunch(b->exec, s);
+        if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
+    }
+    return NSF_OK;
+}
+
+int nsf_batch_step_eager(nsf_batch* b, int32_t nsteps, void* stream) {
+    if (!b || nsteps < 0) return bfail(NSF_EINVAL, "batch_step_eager: bad handle or nsteps");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < nsteps; ++i) {
+        TimerScope ts("batch_step", s);
+        if (b->precision == NSF_F64) enqueue_step<double>(b, s);
+        else enqueue_step<float>(b, s);
+    }
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? NSF_OK : bfail(NSF_EHIP, hipGetErrorString(e));
+}
+
+int nsf_batch_diagnostics(nsf_batch* b, double* out, void* stream) {
+    if (!b || !out) return bfail(NSF_EINVAL, "batch_diagnostics: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    for (int i = 0; i < b->count; ++i) {
+        const Dims& d = b->dims[i];
+        const nsf_phys& p = b->phys[i];
+        const Coef<double> c = make_coef<double>(d, p.Re, p.Ma, p.Pr, p.gamma);
+        double* o = b->diag_out + (size_t)i * NSF_NDIAG;
+        if (b->precision == NSF_F64) launch_diag<double>(d, c, (const double*)b->q[i], b->diag_partial[i], o, s);
+        else launch_diag<float>(d, c, (const float*)b->q[i], b->diag_partial[i], o, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, b->diag_out, (size_t)b->count * NSF_NDIAG * sizeof(double),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
+    for (int i = 0; i < b->count; ++i)
+        if (out[(size_t)i * NSF_NDIAG + 14] > 0) return bfail(NSF_ENONFINITE, "batch: non-finite values");
+    return NSF_OK;
+}
+
+int nsf_batch_info(const nsf_batch* b, int32_t* nitems, int32_t* nblocks) {
+    if (!b || !nitems || !nblocks) return bfail(NSF_EINVAL, "batch_info: NULL argument");
+    *nitems = b->nitems;
+    *nblocks = b->nblocks;
+    return NSF_OK;
+}
+
+int nsf_batch_destroy(nsf_batch* b) {
+    if (!b) return NSF_OK;
+    release(b);
+    return NSF_OK;
+}
+
+}  // extern "C"

@@ -22,6 +22,9 @@ struct StageCoef {
     int last;     // 1 on the third substep: q = q_acc after the update
 };
 
+// Record an error message for nsf_last_error() and return `code`.
+int set_error(int code, const char* msg);
+
 // Launch-time kernel timer (nsf_timer_*): brackets launches of the enabled
 // kernel family with HIP events on the launch stream.
 struct TimerScope {
@@ -66,8 +69,45 @@ template <typename T>
 void launch_ss_naive(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
                      T* r, hipStream_t s);
 
+// Arguments of one tile sweep (nsf_zsweep.hip): residual to r, or (fused)
+// the stage update qout / qacc from the state q.
+template <typename T>
+struct ZArgs {
+    Dims d;
+    Coef<T> k;
+    const T* q;
+    const T* prim;
+    T* r;
+    T* qout;
+    double* qacc;
+    double a_dt, b_dt;
+    int last;
+    int zchunk, tiles_x, tiles_y;
+};
+
+// One instance of a batch: its grid, constants, the three state buffers of
+// the fused stage rotation (q -> qb -> qc -> q), the accumulator and dt.
+template <typename T>
+struct BatchDesc {
+    Dims d;
+    Coef<T> k;
+    T* q;
+    T* qb;
+    T* qc;
+    double* qacc;
+    double dt;
+    int zchunk, tiles_x, tiles_y, tiles;
+};
+
 // z-marching tiled residual kernels (nsf_zsweep.hip)
 int default_zchunk(const Dims& d);
+void tile_counts(const Dims& d, int zchunk, int* tx, int* ty, int* tz, int* zc);
+// Persistent batched fused stage: items[i] = (instance, tile index).
+template <typename T>
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
+                     int nblocks, hipStream_t s);
+template <typename T>
+int batch_blocks_per_cu();
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
                       int zchunk, hipStream_t s);

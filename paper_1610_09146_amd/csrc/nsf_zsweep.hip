@@ -24,6 +24,7 @@ namespace nsf {
 namespace {
 
 constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
+constexpr int kTX = 32, kTY = 8;  // x-y tile of the z-sweeping kernels
 
 __device__ __forceinline__ int pmod(int a, int n) {
     int r = a % n;
@@ -192,20 +193,6 @@ __device__ __forceinline__ T D2(T m2, T m1, T c, T p1, T p2, T b0, T b1, T b2) {
 
 }  // namespace
 
-template <typename T>
-struct ZArgs {
-    Dims d;
-    Coef<T> k;
-    const T* q;
-    const T* prim;
-    T* r;
-    T* qout;
-    double* qacc;
-    double a_dt, b_dt;
-    int last;
-    int zchunk, tiles_x, tiles_y;
-};
-
 namespace {
 
 // Running sums of the residual (paper Section 2, residual assembly), folded
@@ -275,22 +262,23 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
 
+constexpr int kRing = 5;
+
+// One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
+// holds 7 * NPL and sV kRing * 3 * NPL values. Ends with a barrier, so the
+// caller may reuse the LDS for another tile right away.
 template <typename T, int TX, int TY, bool FUSED>
-__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
-                               amdgpu_waves_per_eu(2, 2)))
-k_ra_zsweep(ZArgs<T> A) {
+__device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
+                                            T* __restrict__ sV) {
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
-    constexpr int RING = 5;
-    __shared__ T sP[7 * NPL];         // rho, m0, m1, m2, E, p, T of plane z
-    __shared__ T sV[RING * 3 * NPL];  // ring slot (plane mod 5) x {u, v, w}
+    constexpr int RING = kRing;
 
     const Dims d = A.d;
     const Coef<T> k = A.k;
     const size_t n = d.npts;
     const size_t plane = (size_t)d.nx * d.ny;
 
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tix = t % A.tiles_x;
     const int tiy = (t / A.tiles_x) % A.tiles_y;
     const int tiz = t / (A.tiles_x * A.tiles_y);
@@ -536,6 +524,55 @@ k_ra_zsweep(ZArgs<T> A) {
 }
 
 template <typename T, int TX, int TY, bool FUSED>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
+                               amdgpu_waves_per_eu(2, 2)))
+k_ra_zsweep(ZArgs<T> A) {
+    using G = Geom<TX, TY>;
+    __shared__ T sP[7 * G::NPL];
+    __shared__ T sV[kRing * 3 * G::NPL];
+    zsweep_tile<T, TX, TY, FUSED>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV);
+}
+
+// Persistent batched stage kernel: every workgroup walks the work list of
+// (instance, tile) items. Workgroup g (on XCD g mod 8) takes, in round r,
+// item r*G + (g mod 8)*(G/8) + g/8, so each XCD sweeps a contiguous band of
+// tiles per round. Stage s reads state s of the rotation q -> qb -> qc -> q.
+template <typename T, int TX, int TY>
+__global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
+                               amdgpu_waves_per_eu(2, 2)))
+k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items, int nitems,
+           int stage) {
+    using G = Geom<TX, TY>;
+    __shared__ T sP[7 * G::NPL];
+    __shared__ T sV[kRing * 3 * G::NPL];
+    const int nb = gridDim.x;
+    const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
+    const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
+    const double B_[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
+    for (int base = 0; base < nitems; base += nb) {
+        const int item = base + slot;
+        if (item >= nitems) break;
+        const int2 it = items[item];
+        const BatchDesc<T>& bd = desc[it.x];
+        ZArgs<T> A;
+        A.d = bd.d;
+        A.k = bd.k;
+        A.q = stage == 0 ? bd.q : (stage == 1 ? bd.qb : bd.qc);
+        A.qout = stage == 0 ? bd.qb : (stage == 1 ? bd.qc : bd.q);
+        A.prim = nullptr;
+        A.r = nullptr;
+        A.qacc = bd.qacc;
+        A.a_dt = stage < 2 ? A_[stage] * bd.dt : 0.0;
+        A.b_dt = B_[stage] * bd.dt;
+        A.last = stage == 2;
+        A.zchunk = bd.zchunk;
+        A.tiles_x = bd.tiles_x;
+        A.tiles_y = bd.tiles_y;
+        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV);
+    }
+}
+
+template <typename T, int TX, int TY, bool FUSED>
 void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     ZArgs<T> a = a0;
     const Dims& d = a.d;
@@ -551,6 +588,14 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
 
 int default_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 32 : d.nz); }
 
+void tile_counts(const Dims& d, int zchunk, int* tx, int* ty, int* tz, int* zc) {
+    const int c = zchunk < 1 ? d.nz : (zchunk > d.nz ? d.nz : zchunk);
+    *zc = c;
+    *tx = (d.nx + kTX - 1) / kTX;
+    *ty = (d.ny + kTY - 1) / kTY;
+    *tz = (d.nz + c - 1) / c;
+}
+
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
                       int zchunk, hipStream_t s) {
@@ -561,7 +606,24 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.q = q;
     a.prim = prim;
     a.r = r;
-    launch_tiles<T, 32, 8, false>(a, zchunk, s);
+    launch_tiles<T, kTX, kTY, false>(a, zchunk, s);
+}
+
+template <typename T>
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
+                     int nblocks, hipStream_t s) {
+    TimerScope ts("ra_batch", s);
+    hipLaunchKernelGGL((k_ra_batch<T, kTX, kTY>), dim3(nblocks), dim3(kTX * kTY), 0, s, desc, items,
+                       nitems, stage);
+}
+
+template <typename T>
+int batch_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, kTY>, kTX * kTY, 0) !=
+        hipSuccess)
+        return 0;
+    return nb;
 }
 
 template <typename T>
@@ -577,10 +639,13 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
-    launch_tiles<T, 32, 8, true>(a, zchunk, s);
+    launch_tiles<T, kTX, kTY, true>(a, zchunk, s);
 }
 
 #define NSF_INST(T)                                                                          \
+    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, int, int, int,        \
+                                     hipStream_t);                                            \
+    template int batch_blocks_per_cu<T>();                                                    \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
                                       int, hipStream_t);                                    \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \

@@ -87,6 +87,15 @@ def lib() -> ctypes.CDLL:
         L.nsf_timer_enable.argtypes = [ctypes.c_char_p]
         L.nsf_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(d)]
         L.nsf_timer_names.restype = ctypes.c_char_p
+        L.nsf_batch_workspace_bytes.argtypes = [i32, G, ctypes.c_int, ctypes.POINTER(sz)]
+        L.nsf_batch_create.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int,
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
+                                       ctypes.POINTER(vp)]
+        L.nsf_batch_step.argtypes = [vp, i32, vp]
+        L.nsf_batch_step_eager.argtypes = [vp, i32, vp]
+        L.nsf_batch_diagnostics.argtypes = [vp, ctypes.POINTER(d), vp]
+        L.nsf_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.nsf_batch_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -259,3 +268,71 @@ class Solver:
 
     def diagnostics(self, check: bool = True) -> np.ndarray:
         return diagnostics(self.shape, self.phys, self.precision, self.q, self.work, check=check)
+
+
+class Batch:
+    """Batched form: independent Taylor-Green instances of uneven grids and
+    parameters advanced together (one persistent launch per RK stage, the
+    step captured in a hipGraph). ``instances`` is a list of dicts with
+    ``shape``, ``phys``, ``tgv`` and ``dt`` (see workloads.batch_instances).
+    Per-instance q / q_acc tensors and the shared work buffer are allocated
+    with torch and kept alive by this object."""
+
+    def __init__(self, instances, precision="f64", device="cuda", stream=None):
+        self.instances = list(instances)
+        self.precision = _precision(precision)
+        self.count = len(self.instances)
+        dt = field_dtype(precision)
+        self.q, self.q_acc = [], []
+        for inst in self.instances:
+            nx, ny, nz = inst["shape"]
+            q = torch.empty((5, nz, ny, nx), dtype=dt, device=device)
+            qa = torch.empty((5, nz, ny, nx), dtype=torch.float64, device=device)
+            init_fields(inst["shape"], inst["phys"], inst["tgv"], precision, q, qa, stream)
+            self.q.append(q)
+            self.q_acc.append(qa)
+        grids = (Grid * self.count)(*[_grid(i["shape"]) for i in self.instances])
+        phys = (Phys * self.count)(*[_phys(i["phys"]) for i in self.instances])
+        dts = (ctypes.c_double * self.count)(*[float(i["dt"]) for i in self.instances])
+        qp = (ctypes.c_void_p * self.count)(*[t.data_ptr() for t in self.q])
+        ap = (ctypes.c_void_p * self.count)(*[t.data_ptr() for t in self.q_acc])
+        nb = ctypes.c_size_t(0)
+        L = lib()
+        _check(L.nsf_batch_workspace_bytes(self.count, grids, self.precision, ctypes.byref(nb)),
+               "nsf_batch_workspace_bytes")
+        self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        handle = ctypes.c_void_p(0)
+        torch.cuda.synchronize()
+        _check(L.nsf_batch_create(self.count, grids, phys, dts, self.precision, qp, ap,
+                                  _ptr(self.work), int(nb.value), _stream(stream),
+                                  ctypes.byref(handle)), "nsf_batch_create")
+        self.handle = handle
+
+    def step(self, nsteps: int = 1, graph: bool = True, stream=None) -> None:
+        fn = lib().nsf_batch_step if graph else lib().nsf_batch_step_eager
+        _check(fn(self.handle, int(nsteps), _stream(stream)), "nsf_batch_step")
+
+    def diagnostics(self, stream=None) -> np.ndarray:
+        out = (ctypes.c_double * (self.count * NDIAG))()
+        _check(lib().nsf_batch_diagnostics(self.handle, out, _stream(stream)),
+               "nsf_batch_diagnostics")
+        return np.array(out[:], dtype=np.float64).reshape(self.count, NDIAG)
+
+    def info(self) -> tuple[int, int]:
+        a, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().nsf_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b)), "nsf_batch_info")
+        return int(a.value), int(b.value)
+
+    def points(self) -> int:
+        return sum(int(np.prod(i["shape"])) for i in self.instances)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().nsf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
