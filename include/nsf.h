@@ -100,7 +100,8 @@ typedef struct {
 } nsf_tgv;
 
 /* Implementation knobs (not part of the method). Pass NULL for defaults.
- *   block_x, block_y: x-y tile of the stencil kernels (0 = default);
+ *   block_x, block_y: x-y tile of the z-sweeping kernels: block_x is 32,
+ *         block_y 8 or 16 (0 = default);
  *   zchunk: planes marched per workgroup by the z-sweeping kernels (0 = default);
  *   fuse: RA/SN only. 0 = primitives stored by their own kernel and the RK
  *         update a separate kernel, as in the paper; 1 = primitives
@@ -180,6 +181,13 @@ int nsf_batch_workspace_bytes(int32_t count, const nsf_grid *grids, int precisio
 int nsf_batch_create(int32_t count, const nsf_grid *grids, const nsf_phys *phys, const double *dt,
                      int precision, void *const *q, double *const *q_acc, void *work,
                      size_t work_bytes, void *stream, nsf_batch **out);
+
+/* As nsf_batch_create with implementation knobs (block_y selects the tile
+ * height 8 or 16 of the stage kernel; other fields are ignored). */
+int nsf_batch_create_tuned(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
+                           const double *dt, int precision, const nsf_tuning *tune, void *const *q,
+                           double *const *q_acc, void *work, size_t work_bytes, void *stream,
+                           nsf_batch **out);
 
 /* Advance every instance nsteps steps by replaying the captured graph on
  * `stream`. Asynchronous. */

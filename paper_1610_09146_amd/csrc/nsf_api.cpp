@@ -121,6 +121,14 @@ struct Layout {
     bool fused = false;
 };
 
+int zchunk_of(const Dims& d, const nsf_tuning* tune) {
+    return tune && tune->zchunk > 0 ? tune->zchunk : default_zchunk(d);
+}
+
+int tile_y_of(const Dims& d, const nsf_tuning* tune, int es) {
+    return tune && (tune->block_y == 8 || tune->block_y == 16) ? tune->block_y : default_tile_y(es, d);
+}
+
 bool wants_fused(int variant, const nsf_tuning* tune) {
     return (variant == NSF_RA || variant == NSF_SN) && tune && tune->fuse && !tune->naive;
 }
@@ -240,7 +248,7 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
         case NSF_SN:
             launch_prims<T>(d, c, q, prim, s);
             if (tune && tune->naive) launch_ra_naive<T>(d, c, q, prim, r, s);
-            else launch_ra_zsweep<T>(d, c, q, prim, r, tune && tune->zchunk ? tune->zchunk : default_zchunk(d), s);
+            else launch_ra_zsweep<T>(d, c, q, prim, r, zchunk_of(d, tune), tile_y_of(d, tune, sizeof(T)), s);
             break;
         case NSF_SS:
         case NSF_RS: {
@@ -263,7 +271,8 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
     static const double B[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
     if (L.fused) {
         const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
-        const int zc = tune->zchunk ? tune->zchunk : default_zchunk(d);
+        const int zc = zchunk_of(d, tune);
+        const int ty = tile_y_of(d, tune, sizeof(T));
         T* qb = (T*)(work + L.qb);
         T* qc = (T*)(work + L.qc);
         T* in[3] = {q, qb, qc};
@@ -274,7 +283,7 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.a_dt = st < 2 ? A[st] * dt : 0.0;
                 sc.b_dt = B[st] * dt;
                 sc.last = st == 2;
-                launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, s);
+                launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s);
             }
         return check_hip("rk_step launch");
     }

@@ -18,6 +18,7 @@ struct nsf_batch {
     int precision = NSF_F64;
     int nitems = 0;
     int nblocks = 0;
+    int tile_y = 8;
     std::vector<Dims> dims;
     std::vector<nsf_phys> phys;
     std::vector<void*> q;
@@ -79,7 +80,7 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
         bd.qacc = qacc[i];
         bd.dt = dt[i];
         int tx, ty, tz, zc;
-        tile_counts(d, default_zchunk(d), &tx, &ty, &tz, &zc);
+        tile_counts(d, default_zchunk(d), b->tile_y, &tx, &ty, &tz, &zc);
         bd.zchunk = zc;
         bd.tiles_x = tx;
         bd.tiles_y = ty;
@@ -101,7 +102,8 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
 template <typename T>
 void enqueue_step(nsf_batch* b, hipStream_t s) {
     for (int st = 0; st < 3; ++st)
-        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->nitems, st, b->nblocks, s);
+        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->nitems, st, b->nblocks,
+                           b->tile_y, s);
 }
 
 void release(nsf_batch* b) {
@@ -132,7 +134,18 @@ int nsf_batch_workspace_bytes(int32_t count, const nsf_grid* grids, int precisio
 int nsf_batch_create(int32_t count, const nsf_grid* grids, const nsf_phys* phys, const double* dt,
                      int precision, void* const* q, double* const* q_acc, void* work,
                      size_t work_bytes, void* stream, nsf_batch** out) {
+    return nsf_batch_create_tuned(count, grids, phys, dt, precision, nullptr, q, q_acc, work,
+                                  work_bytes, stream, out);
+}
+
+int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
+                           const double* dt, int precision, const nsf_tuning* tune, void* const* q,
+                           double* const* q_acc, void* work, size_t work_bytes, void* stream,
+                           nsf_batch** out) {
     (void)stream;
+    const int tile_y = tune && (tune->block_y == 8 || tune->block_y == 16)
+                           ? tune->block_y
+                           : (precision == NSF_F64 ? 16 : 8);
     if (!out) return bfail(NSF_EINVAL, "batch: out NULL");
     *out = nullptr;
     std::vector<Dims> dims;
@@ -157,6 +170,7 @@ int nsf_batch_create(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
     b->phys.assign(phys, phys + count);
     b->q.assign(q, q + count);
     b->diag_partial.resize(count);
+    b->tile_y = tile_y;
     rc = precision == NSF_F64
              ? build_tables<double>(b, dims, phys, dt, q, q_acc, (char*)work)
              : build_tables<float>(b, dims, phys, dt, q, q_acc, (char*)work);
@@ -164,7 +178,8 @@ int nsf_batch_create(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = precision == NSF_F64 ? batch_blocks_per_cu<double>() : batch_blocks_per_cu<float>();
+    const int per_cu = precision == NSF_F64 ? batch_blocks_per_cu<double>(b->tile_y)
+                                            : batch_blocks_per_cu<float>(b->tile_y);
     if (e != hipSuccess || cus < 1 || per_cu < 1) { release(b); return bfail(NSF_EHIP, "batch: occupancy query failed"); }
     b->nblocks = (cus * per_cu) / 8 * 8;  // a multiple of the XCD count
     if (b->nblocks < 8) b->nblocks = 8;

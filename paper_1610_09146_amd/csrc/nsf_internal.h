@@ -100,23 +100,25 @@ struct BatchDesc {
 };
 
 // z-marching tiled residual kernels (nsf_zsweep.hip)
+// Tiles are 32 x tile_y (tile_y = 8 or 16) columns; zchunk planes deep.
 int default_zchunk(const Dims& d);
-void tile_counts(const Dims& d, int zchunk, int* tx, int* ty, int* tz, int* zc);
+int default_tile_y(int precision_bytes, const Dims& d);
+void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* tz, int* zc);
 // Persistent batched fused stage: items[i] = (instance, tile index).
 template <typename T>
 void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
-                     int nblocks, hipStream_t s);
+                     int nblocks, int tile_y, hipStream_t s);
 template <typename T>
-int batch_blocks_per_cu();
+int batch_blocks_per_cu(int tile_y);
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, hipStream_t s);
+                      int zchunk, int tile_y, hipStream_t s);
 // Fused RA stage: primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),
 // q_acc += B dt R. qout must not alias q.
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, hipStream_t s);
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s);
 
 // diagnostics (nsf_diag.hip); partial holds diag_partial_count(d) * NDIAG doubles
 size_t diag_partial_count(const Dims& d);

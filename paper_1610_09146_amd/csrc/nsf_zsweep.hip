@@ -24,7 +24,7 @@ namespace nsf {
 namespace {
 
 constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
-constexpr int kTX = 32, kTY = 8;  // x-y tile of the z-sweeping kernels
+constexpr int kTX = 32;  // tile width; the tile height is 8 or 16 rows
 
 __device__ __forceinline__ int pmod(int a, int n) {
     int r = a % n;
@@ -265,11 +265,15 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
 constexpr int kRing = 5;
 
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
-// holds 7 * NPL and sV kRing * 3 * NPL values. Ends with a barrier, so the
-// caller may reuse the LDS for another tile right away.
+// holds 7 * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
+// 3 * 5 * NHALO values: the raw conservative values each thread loaded at
+// its halo point for planes z .. z+2 (a per-thread ring kept in LDS, so
+// every halo point is fetched once per plane, in the same iteration in
+// which the neighbouring tile fetches it as interior). Ends with a
+// barrier, so the caller may reuse the LDS for another tile right away.
 template <typename T, int TX, int TY, bool FUSED>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
-                                            T* __restrict__ sV) {
+                                            T* __restrict__ sV, T* __restrict__ sH) {
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -331,6 +335,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         yw = D1(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX], k.a1[1], k.a2[1]);
     };
 
+    // per-thread halo ring (fused form): slot of plane zz, field f
+    auto hring = [&](int zz, int f, int h) -> T& {
+        return sH[(pmod(zz, 3) * 5 + f) * NHALO + tid + h * NT];
+    };
+
     // preamble: ring planes z0-2 .. z0+1 and their queued in-plane derivatives
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -342,10 +351,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
-                RawV<T, FUSED> rv;
-                load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
                 T u, v, w;
-                finish_v<T, FUSED>(rv, u, v, w);
+                if constexpr (FUSED) {
+                    RawP<T, FUSED> rp;
+                    load_rawp<T, FUSED>(rp, A.q, A.prim, n, poff(zz) + hcol[h]);
+                    const T ir = fast_rcp(rp.a[0]);
+                    u = rp.a[1] * ir;
+                    v = rp.a[2] * ir;
+                    w = rp.a[3] * ir;
+                    if (s >= 2)
+#pragma unroll
+                        for (int f = 0; f < 5; ++f) hring(zz, f, h) = rp.a[f];
+                } else {
+                    RawV<T, FUSED> rv;
+                    load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
+                    finish_v<T, FUSED>(rv, u, v, w);
+                }
                 V[hidx[h]] = u;
                 V[NPL + hidx[h]] = v;
                 V[2 * NPL + hidx[h]] = w;
@@ -354,14 +375,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         leading(V, Xs[s], Xw[s], Yw[s]);
     }
 
-    // prefetched halo values for the first iteration
-    RawV<T, FUSED> hv[HPT];
-    RawP<T, FUSED> hp[HPT];
+    // prefetched halo values for the first iteration: fused form, raw q of
+    // plane z0+2; stored-primitive form, velocity of plane z0+2 and the
+    // seven plane fields of plane z0
+    RawP<T, FUSED> hq[HPT];
+    RawV<T, FUSED> hv[FUSED ? 1 : HPT];
 #pragma unroll
     for (int h = 0; h < HPT; ++h)
         if (hval[h]) {
-            load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
-            load_rawp<T, FUSED>(hp[h], A.q, A.prim, n, poff(z0) + hcol[h]);
+            if constexpr (FUSED) {
+                load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+            } else {
+                load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+                load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0) + hcol[h]);
+            }
         }
 
     for (int z = z0; z < z1; ++z) {
@@ -383,12 +410,27 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
                 T u, v, w;
-                finish_v<T, FUSED>(hv[h], u, v, w);
+                T f7[7];
+                if constexpr (FUSED) {
+                    // velocity of the leading plane from the raw values of z+2
+                    const T ir = fast_rcp(hq[h].a[0]);
+                    u = hq[h].a[1] * ir;
+                    v = hq[h].a[2] * ir;
+                    w = hq[h].a[3] * ir;
+                    // plane-z fields from the raw values parked two planes ago
+                    RawP<T, FUSED> rz;
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) rz.a[f] = hring(z, f, h);
+                    finish_p<T, FUSED>(rz, k, f7);
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) hring(z + 2, f, h) = hq[h].a[f];
+                } else {
+                    finish_v<T, FUSED>(hv[h], u, v, w);
+                    finish_p<T, FUSED>(hq[h], k, f7);
+                }
                 Vl[hidx[h]] = u;
                 Vl[NPL + hidx[h]] = v;
                 Vl[2 * NPL + hidx[h]] = w;
-                T f7[7];
-                finish_p<T, FUSED>(hp[h], k, f7);
 #pragma unroll
                 for (int f = 0; f < 7; ++f) sP[f * NPL + hidx[h]] = f7[f];
             }
@@ -398,8 +440,12 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
-                load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
-                load_rawp<T, FUSED>(hp[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                if constexpr (FUSED) {
+                    load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                } else {
+                    load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                    load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                }
             }
         __syncthreads();
 
@@ -523,14 +569,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     }
 }
 
+// Waves per SIMD the register budget is tuned for: double-precision tiles
+// need up to 256 VGPRs (two waves), single precision fits three.
+template <typename T>
+struct Occ {
+    static constexpr int kWaves = sizeof(T) == 8 ? 2 : 3;
+};
+
 template <typename T, int TX, int TY, bool FUSED>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
-                               amdgpu_waves_per_eu(2, 2)))
+                               amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[7 * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
-    zsweep_tile<T, TX, TY, FUSED>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV);
+    __shared__ T sH[FUSED ? 15 * G::NHALO : 1];
+    zsweep_tile<T, TX, TY, FUSED>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH);
 }
 
 // Persistent batched stage kernel: every workgroup walks the work list of
@@ -539,12 +593,13 @@ k_ra_zsweep(ZArgs<T> A) {
 // tiles per round. Stage s reads state s of the rotation q -> qb -> qc -> q.
 template <typename T, int TX, int TY>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
-                               amdgpu_waves_per_eu(2, 2)))
+                               amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
 k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items, int nitems,
            int stage) {
     using G = Geom<TX, TY>;
     __shared__ T sP[7 * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
+    __shared__ T sH[15 * G::NHALO];
     const int nb = gridDim.x;
     const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
@@ -568,7 +623,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.zchunk = bd.zchunk;
         A.tiles_x = bd.tiles_x;
         A.tiles_y = bd.tiles_y;
-        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV);
+        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV, sH);
     }
 }
 
@@ -588,17 +643,24 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
 
 int default_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 32 : d.nz); }
 
-void tile_counts(const Dims& d, int zchunk, int* tx, int* ty, int* tz, int* zc) {
+// Double precision: 32 x 16 tiles (one 512-thread workgroup per CU, fewest
+// halo points per output point); single precision: 32 x 8 (three
+// 256-thread workgroups per CU).
+int default_tile_y(int precision_bytes, const Dims& d) {
+    return (precision_bytes == 8 && d.ny >= 16) ? 16 : 8;
+}
+
+void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* tz, int* zc) {
     const int c = zchunk < 1 ? d.nz : (zchunk > d.nz ? d.nz : zchunk);
     *zc = c;
     *tx = (d.nx + kTX - 1) / kTX;
-    *ty = (d.ny + kTY - 1) / kTY;
+    *ty = (d.ny + tile_y - 1) / tile_y;
     *tz = (d.nz + c - 1) / c;
 }
 
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, hipStream_t s) {
+                      int zchunk, int tile_y, hipStream_t s) {
     TimerScope ts("ra_zsweep", s);
     ZArgs<T> a{};
     a.d = d;
@@ -606,29 +668,34 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.q = q;
     a.prim = prim;
     a.r = r;
-    launch_tiles<T, kTX, kTY, false>(a, zchunk, s);
+    if (tile_y == 16) launch_tiles<T, kTX, 16, false>(a, zchunk, s);
+    else launch_tiles<T, kTX, 8, false>(a, zchunk, s);
 }
 
 template <typename T>
 void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
-                     int nblocks, hipStream_t s) {
+                     int nblocks, int tile_y, hipStream_t s) {
     TimerScope ts("ra_batch", s);
-    hipLaunchKernelGGL((k_ra_batch<T, kTX, kTY>), dim3(nblocks), dim3(kTX * kTY), 0, s, desc, items,
-                       nitems, stage);
+    if (tile_y == 16)
+        hipLaunchKernelGGL((k_ra_batch<T, kTX, 16>), dim3(nblocks), dim3(kTX * 16), 0, s, desc,
+                           items, nitems, stage);
+    else
+        hipLaunchKernelGGL((k_ra_batch<T, kTX, 8>), dim3(nblocks), dim3(kTX * 8), 0, s, desc, items,
+                           nitems, stage);
 }
 
 template <typename T>
-int batch_blocks_per_cu() {
+int batch_blocks_per_cu(int tile_y) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, kTY>, kTX * kTY, 0) !=
-        hipSuccess)
-        return 0;
-    return nb;
+    hipError_t e = tile_y == 16
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16>, kTX * 16, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 8>, kTX * 8, 0);
+    return e == hipSuccess ? nb : 0;
 }
 
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, hipStream_t s) {
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s) {
     TimerScope ts("ra_fused", s);
     ZArgs<T> a{};
     a.d = d;
@@ -639,17 +706,18 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
-    launch_tiles<T, kTX, kTY, true>(a, zchunk, s);
+    if (tile_y == 16) launch_tiles<T, kTX, 16, true>(a, zchunk, s);
+    else launch_tiles<T, kTX, 8, true>(a, zchunk, s);
 }
 
 #define NSF_INST(T)                                                                          \
-    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, int, int, int,        \
+    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, int, int, int, int,   \
                                      hipStream_t);                                            \
-    template int batch_blocks_per_cu<T>();                                                    \
+    template int batch_blocks_per_cu<T>(int);                                                 \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
-                                      int, hipStream_t);                                    \
+                                      int, int, hipStream_t);                               \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
-                                     const StageCoef&, int, hipStream_t);
+                                     const StageCoef&, int, int, hipStream_t);
 NSF_INST(float)
 NSF_INST(double)
 #undef NSF_INST

@@ -234,7 +234,8 @@ def test_rhs_large_sampled_planes(n, variant):
 
 # ------------------------------------------------------------ tiled / fused paths
 @pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("tune", [{"naive": 1}, {"zchunk": 7}, {"zchunk": 3}])
+@pytest.mark.parametrize("tune", [{"naive": 1}, {"zchunk": 7}, {"zchunk": 3},
+                                  {"block_y": 8}, {"block_y": 16, "zchunk": 9}])
 def test_rhs_f64_parity_ra_tunings(shape, tune):
     print(f"case rhs_ra_tune {tune} {shape}", flush=True)
     q = perturbed_state(shape)
@@ -261,13 +262,14 @@ def test_rk_fused_ten_steps_tgv32(zchunk):
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 50), (5, 6, 7), (70, 11, 9)])
-def test_rk_fused_matches_unfused(precision, shape):
+@pytest.mark.parametrize("block_y", [8, 16])
+def test_rk_fused_matches_unfused(precision, shape, block_y):
     # the fused stage kernel (primitives recomputed in the tile, update in
     # the epilogue) agrees with the stored-primitive path to round-off
-    print(f"case fused_vs_unfused {precision} {shape}", flush=True)
+    print(f"case fused_vs_unfused {precision} {shape} {block_y}", flush=True)
     tgv = W.tgv_pointwise(17, 1e-2)
     out = {}
-    for name, tune in (("plain", None), ("fused", {"fuse": 1})):
+    for name, tune in (("plain", {"block_y": 8}), ("fused", {"fuse": 1, "block_y": block_y})):
         s = nsf.Solver(shape, PHYS, "RA", precision, tune=tune)
         s.init(tgv)
         s.step(2e-3, 3)
