@@ -40,6 +40,8 @@ FAMILY_BYTES = {
     "ra_fused": (160, 120),       # q, q_acc -> q_next, q_acc
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
+    "ss_grad": (96, 48),          # u, v, w -> 9 gradients
+    "ss_zsweep": (192, 96),       # q, prims, 9 gradients -> r
     "bl_deriv": (16, 8),          # one field -> one derivative
     "bl_product": (24, 12),       # two fields -> one product
     "bl_assemble": (584, 292),    # 60 derivatives, q, u -> r
@@ -55,7 +57,9 @@ def families(variant, tune):
         if tune and tune.get("naive"):
             return ["prims", "ra_naive", "update", "diag"]
         return ["prims", "ra_zsweep", "update", "diag"]
-    return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
+    if tune and tune.get("naive"):
+        return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
+    return ["prims", "ss_grad", "ss_zsweep", "update", "diag"]
 
 
 def log(msg: str) -> None:
@@ -209,8 +213,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--variant", default="RA")
-    ap.add_argument("--fuse", type=int, default=1, help="fused RA stage kernel (1) or not (0)")
+    ap.add_argument("--variant", default="AUTO",
+                    help="AUTO = the autotuner's pick for this grid (default), or BL/RA/SS/SN/RS")
+    ap.add_argument("--fuse", type=int, default=1, help="RA/SN: fused stage kernel (1) or not (0)")
     ap.add_argument("--no-extras", action="store_true", help="skip BL/SS/FP32 side measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -238,9 +243,18 @@ def main() -> int:
         log("copy calibration: 3 x 1 GiB")
         del src, dst
     n = args.n
-    main_tune = {"fuse": args.fuse} if args.variant in ("RA", "SN") else None
-    log(f"main: {args.variant} {main_tune} f64 n={n} steps={args.steps}")
-    main_res = run_variant(nsf, torch, W, n, args.variant, "f64", args.steps, args.warmup,
+    tuned = {}
+    if args.variant == "AUTO":
+        for prec in ("f64", "f32"):
+            log(f"autotune {n}^3 {prec}")
+            tuned[prec] = nsf.autotune((n, n, n), W.TGV_PHYS, prec, quick=True, steps=2)
+            log(f"  -> {tuned[prec]}")
+        main_variant, main_tune = tuned["f64"]["variant"], tuned["f64"]["tune"]
+    else:
+        main_variant = args.variant
+        main_tune = {"fuse": args.fuse} if args.variant in ("RA", "SN") else None
+    log(f"main: {main_variant} {main_tune} f64 n={n} steps={args.steps}")
+    main_res = run_variant(nsf, torch, W, n, main_variant, "f64", args.steps, args.warmup,
                            tune=main_tune)
     log(f"main done: {main_res['pt_rhs_per_s']:.3e} pt-RHS/s")
     extras = {}
@@ -248,7 +262,9 @@ def main() -> int:
         for name, v, prec, k, tune in (("BL_f64", "BL", "f64", 3, None),
                                        ("SS_f64", "SS", "f64", 5, None),
                                        ("RA_f64_stored_prims", "RA", "f64", 5, None),
-                                       ("RA_f32_fused", "RA", "f32", 10, {"fuse": 1})):
+                                       ("RA_f32_fused", "RA", "f32", 10, {"fuse": 1})) + (
+                (("f32_autotuned", tuned["f32"]["variant"], "f32", 10, tuned["f32"]["tune"]),)
+                if tuned else ()):
             log(f"extra: {name}")
             r = run_variant(nsf, torch, W, n, v, prec, k, 1, tune=tune)
             r["roofline"] = roofline_of(r, prec)
@@ -271,8 +287,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"taylor-green {n}^3 FP64, Re=1600 Ma=0.1 Pr=0.71, "
                                f"dt={W.tgv_dt(n)}, KE+enstrophy every step",
-                   "variant": args.variant, "tune": main_tune, "n": n, "dt": W.tgv_dt(n),
-                   "diag_every": 1},
+                   "variant": main_variant, "tune": main_tune, "selected_by": args.variant,
+                   "n": n, "dt": W.tgv_dt(n), "diag_every": 1},
+        "autotune": tuned,
         "roofline": roofline_of(main_res, "f64"),
         "main": main_res,
         "extras": extras,

@@ -67,7 +67,10 @@ typedef enum {
  *           work arrays, the rest recomputed inline.
  *   NSF_SS  store some: as RS, the non-stored derivatives held in
  *           thread-local values (the paper's fastest CPU algorithm). */
-typedef enum { NSF_BL = 0, NSF_RA = 1, NSF_SS = 2, NSF_SN = 3, NSF_RS = 4 } nsf_variant;
+typedef enum { NSF_BL = 0, NSF_RA = 1, NSF_SS = 2, NSF_SN = 3, NSF_RS = 4, NSF_AUTO = 5 } nsf_variant;
+/* NSF_AUTO: the algorithm and tuning that nsf_autotune (or nsf_tune_load)
+ * recorded for this grid and precision in this process; RA with the fused
+ * stage kernel if nothing was recorded. The tuning argument is ignored. */
 typedef enum { NSF_F64 = 0, NSF_F32 = 1 } nsf_precision;
 
 #define NSF_NDIAG 16
@@ -160,6 +163,37 @@ int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precis
 int nsf_diagnostics(const nsf_grid *g, const nsf_phys *phys, int precision,
                     const void *q, void *work, size_t work_bytes, double *out,
                     void *stream);
+
+/* ---------------------------------------------------------------- autotuner
+ * Searches the paper's store-versus-recompute trade-off (Section 2: which
+ * derivatives to store in work arrays, which to recompute; the
+ * conclusion's point that the best algorithm depends on the machine) made
+ * searchable: algorithm BL / RA (primitives stored, or recomputed in the
+ * tile with the update fused) / SS, crossed with the tile height and
+ * z-chunk of the z-sweeping kernels. Every candidate is first checked
+ * against the untiled reference residual on a seeded perturbed
+ * Taylor-Green state of the same grid (relative max-norm difference at most
+ * 1e-10 in double, 1e-3 in single precision); only passing candidates are
+ * timed (`steps` RK steps each). The winner is recorded for NSF_AUTO and,
+ * if cache_path is not NULL, appended as one JSON line to that file.
+ * Synchronous. Allocates its own device buffers (about 4 states and the
+ * largest candidate's work) for the duration of the call. */
+#define NSF_TUNE_QUICK 1 /* skip BL and the untiled kernels */
+typedef struct {
+    int32_t variant;
+    nsf_tuning tune;
+    double pt_rhs_per_s;   /* measured grid-point residual evaluations/s */
+    double parity_rel_err; /* worst per-field relative difference */
+} nsf_tune_result;
+
+int nsf_autotune(const nsf_grid *g, const nsf_phys *phys, int precision, int flags, int32_t steps,
+                 const char *cache_path, nsf_tune_result *best, void *stream);
+/* Load gfx950 entries of a cache file written by nsf_autotune (later lines
+ * override earlier ones). Returns the number of entries loaded, or an
+ * error status. */
+int nsf_tune_load(const char *cache_path);
+/* The recorded choice for a grid and precision (NSF_EUNSUPPORTED if none). */
+int nsf_tune_get(const nsf_grid *g, int precision, nsf_tune_result *out);
 
 /* ---------------------------------------------------------------- batched form
  * Many independent Taylor-Green-type instances (own grid, parameters, dt)

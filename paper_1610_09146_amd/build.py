@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libnsf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["nsf_api.cpp", "nsf_pointwise.hip", "nsf_naive.hip", "nsf_bl.hip", "nsf_diag.hip",
-           "nsf_zsweep.hip", "nsf_batch.cpp"]
+           "nsf_zsweep.hip", "nsf_batch.cpp", "nsf_grad.hip", "nsf_tune.cpp"]
 
 CFLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

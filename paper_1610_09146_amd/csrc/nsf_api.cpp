@@ -133,7 +133,22 @@ bool wants_fused(int variant, const nsf_tuning* tune) {
     return (variant == NSF_RA || variant == NSF_SN) && tune && tune->fuse && !tune->naive;
 }
 
-bool is_variant(int v) { return v >= NSF_BL && v <= NSF_RS; }
+bool is_variant(int v) { return v >= NSF_BL && v <= NSF_AUTO; }
+
+// NSF_AUTO -> the recorded (or default) algorithm and tuning; `store`
+// receives the tuning when it has to be substituted.
+void resolve(const Dims& d, int precision, int* variant, const nsf_tuning** tune,
+             nsf_tuning* store) {
+    if (*variant != NSF_AUTO) return;
+    int v = NSF_RA;
+    std::memset(store, 0, sizeof *store);
+    if (!tune_lookup(d, precision, &v, store)) {
+        v = NSF_RA;
+        store->fuse = 1;
+    }
+    *variant = v;
+    *tune = store;
+}
 bool is_precision(int p) { return p == NSF_F64 || p == NSF_F32; }
 
 int deriv_arrays(int variant) {
@@ -254,8 +269,14 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
         case NSF_RS: {
             T* grad = (T*)(work + L.deriv);
             launch_prims<T>(d, c, q, prim, s);
-            launch_ss_grad_naive<T>(d, c, prim, grad, s);
-            launch_ss_naive<T>(d, c, q, prim, grad, r, s);
+            if (tune && tune->naive) {
+                launch_ss_grad_naive<T>(d, c, prim, grad, s);
+                launch_ss_naive<T>(d, c, q, prim, grad, r, s);
+            } else {
+                launch_ss_grad<T>(d, c, prim, grad, s);
+                launch_ss_zsweep<T>(d, c, q, prim, grad, r, zchunk_of(d, tune),
+                                    tile_y_of(d, tune, sizeof(T)), s);
+            }
             break;
         }
         default:
@@ -333,6 +354,8 @@ int nsf_workspace_bytes(const nsf_grid* g, int variant, int precision, const nsf
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!bytes) return fail(NSF_EINVAL, "bytes is NULL");
+    nsf_tuning store;
+    resolve(d, precision, &variant, &tune, &store);
     *bytes = layout_for(d, variant, precision, tune).total;
     return NSF_OK;
 }
@@ -372,6 +395,8 @@ int nsf_rhs(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!q || !r || !work) return fail(NSF_EINVAL, "q, r and work must be non-NULL");
+    nsf_tuning store;
+    resolve(d, precision, &variant, &tune, &store);
     const Layout L = layout_for(d, variant, precision, tune);
     if (work_bytes < L.total)
         return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
@@ -396,6 +421,8 @@ int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precis
     if (!q || !q_acc || !r || !work) return fail(NSF_EINVAL, "q, q_acc, r and work must be non-NULL");
     if (nsteps < 0) return fail(NSF_EINVAL, "nsteps %d", nsteps);
     if (!std::isfinite(dt)) return fail(NSF_EINVAL, "dt not finite");
+    nsf_tuning store;
+    resolve(d, precision, &variant, &tune, &store);
     const Layout L = layout_for(d, variant, precision, tune);
     if (work_bytes < L.total)
         return fail(NSF_EWORKSPACE, "work is %zu bytes, need %zu", work_bytes, L.total);
@@ -449,7 +476,7 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ss_grad_naive,"
-    "ss_naive,diag,copy,ra_batch,batch_step";
+    "ss_naive,ss_grad,ss_zsweep,diag,copy,ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

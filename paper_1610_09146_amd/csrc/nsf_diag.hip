@@ -1,9 +1,16 @@
 // Diagnostics of paper Section 3 (kinetic-energy and enstrophy integrals,
 // after DeBonis 2013) plus conservation sums, extrema and a non-finite
-// count. Reduced in double in a fixed order: each thread walks a fixed
-// point sequence, waves reduce with shuffles in a fixed tree, waves combine
-// through LDS, and a second one-block pass folds the per-block partials in
-// index order -- no atomics, so results are bitwise reproducible.
+// count, all in double precision.
+//
+// Pass 1 is a z-marching tile kernel: a workgroup owns a 32 x 8 column tile
+// and a chunk of planes; the velocity of every plane it touches is computed
+// once from q and kept, with a two-point x-y halo, in a five-plane LDS ring,
+// from which the fourth-order first derivatives (hence the vorticity) of
+// the centre plane are formed. Pointwise quantities are accumulated as each
+// plane enters the ring. Reductions run in a fixed order -- per-thread
+// plane order, wave shuffles, LDS across waves, then a one-block pass over
+// the per-tile partials in tile order -- with no atomics, so results are
+// bitwise reproducible for a given grid.
 #include <math.h>
 
 #include "nsf_internal.h"
@@ -12,9 +19,22 @@ namespace nsf {
 
 namespace {
 
-constexpr int kThreads = 256;
-constexpr int kMaxBlocks = 2048;
+constexpr int kTX = 32, kTY = 8, kNT = kTX * kTY;
+constexpr int kLX = kTX + 4, kLY = kTY + 4, kNPL = kLX * kLY, kNHALO = kNPL - kNT;
+constexpr int kRing = 5;
 constexpr int kND = 16;
+constexpr int kXCD = 8;
+
+__device__ __forceinline__ int pmodi(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int per = nb / kXCD, extra = nb % kXCD;
+    const int x = bid % kXCD, k = bid / kXCD;
+    return x * per + (x < extra ? x : extra) + k;
+}
 
 // slot kinds: sums 0..6, 15; maxima 7..11; minima 12, 13; count 14 (a sum)
 __device__ __forceinline__ bool is_max(int s) { return s >= 7 && s <= 11; }
@@ -27,14 +47,13 @@ __device__ __forceinline__ double combine(int s, double a, double b) {
 }
 
 __device__ __forceinline__ double identity(int s) {
-    if (is_max(s)) return 0.0;
     if (is_min(s)) return INFINITY;
     return 0.0;
 }
 
-// Reduce acc[kND] over the block in a fixed order; thread 0 returns it.
-__device__ void block_reduce(double acc[kND]) {
-    __shared__ double sh[kThreads / 64][kND];
+// Reduce acc[kND] over the block in a fixed order; thread 0 gets the result.
+template <int NTHREADS>
+__device__ void block_reduce(double acc[kND], double* sh /* [NTHREADS/64][kND] */) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int s = 0; s < kND; ++s) {
@@ -45,108 +64,164 @@ __device__ void block_reduce(double acc[kND]) {
     }
     if (lane == 0)
 #pragma unroll
-        for (int s = 0; s < kND; ++s) sh[wave][s] = acc[s];
+        for (int s = 0; s < kND; ++s) sh[wave * kND + s] = acc[s];
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
         for (int s = 0; s < kND; ++s) {
-            double v = sh[0][s];
-            for (int w = 1; w < kThreads / 64; ++w) v = combine(s, v, sh[w][s]);
+            double v = sh[s];
+            for (int w = 1; w < NTHREADS / 64; ++w) v = combine(s, v, sh[w * kND + s]);
             acc[s] = v;
         }
 }
 
-template <typename T>
-__device__ __forceinline__ void vel_at(const T* __restrict__ q, size_t n, size_t e, double v[3]) {
-    const double ir = 1.0 / (double)q[e];
-    v[0] = (double)q[n + e] * ir;
-    v[1] = (double)q[2 * n + e] * ir;
-    v[2] = (double)q[3 * n + e] * ir;
+__device__ __forceinline__ void halo_pos(int h, int& hx, int& hy) {
+    constexpr int ROWS2 = 2 * kLX;
+    if (h < ROWS2) {
+        hy = h / kLX;
+        hx = h % kLX;
+    } else if (h < 2 * ROWS2) {
+        const int t = h - ROWS2;
+        hy = kTY + 2 + t / kLX;
+        hx = t % kLX;
+    } else {
+        const int t = h - 2 * ROWS2;
+        hy = 2 + t / 4;
+        const int c = t % 4;
+        hx = c < 2 ? c : kTX + c;
+    }
 }
 
+struct DiagArgs {
+    Dims d;
+    Coef<double> c;
+    int zchunk, tiles_x, tiles_y;
+};
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_diag_partial(Dims d, Coef<double> c, const T* __restrict__ q,
-                                                           double* __restrict__ partial) {
+__global__ void __launch_bounds__(kNT) k_diag_partial(DiagArgs A, const T* __restrict__ q,
+                                                      double* __restrict__ partial) {
+    __shared__ double sV[kRing * 3 * kNPL];
+    __shared__ double sRed[(kNT / 64) * kND];
+    const Dims d = A.d;
+    const size_t n = d.npts;
+    const size_t plane = (size_t)d.nx * d.ny;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
+    const int tix = t % A.tiles_x;
+    const int tiy = (t / A.tiles_x) % A.tiles_y;
+    const int tiz = t / (A.tiles_x * A.tiles_y);
+    const int x0 = tix * kTX, y0 = tiy * kTY, z0 = tiz * A.zchunk;
+    const int z1 = min(z0 + A.zchunk, d.nz);
+    const int tid = threadIdx.x;
+    const int lx = tid % kTX, ly = tid / kTX;
+    const bool active = x0 + lx < d.nx && y0 + ly < d.ny;
+    const size_t col = (size_t)pmodi(y0 + ly, d.ny) * d.nx + pmodi(x0 + lx, d.nx);
+    const int own = (ly + 2) * kLX + (lx + 2);
+    const bool hval = tid < kNHALO;
+    int hidx = 0;
+    size_t hcol = 0;
+    if (hval) {
+        int hx, hy;
+        halo_pos(tid, hx, hy);
+        hidx = hy * kLX + hx;
+        hcol = (size_t)pmodi(y0 + hy - 2, d.ny) * d.nx + pmodi(x0 + hx - 2, d.nx);
+    }
+    const double gm1 = A.c.gm1;
+
     double acc[kND];
 #pragma unroll
     for (int s = 0; s < kND; ++s) acc[s] = identity(s);
-    const size_t n = d.npts;
-    const size_t stride = (size_t)gridDim.x * kThreads;
-    const double gm1 = c.gm1;
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += stride) {
-        const int i = (int)(e % (size_t)d.nx);
-        const int j = (int)((e / (size_t)d.nx) % (size_t)d.ny);
-        const int k = (int)(e / ((size_t)d.nx * d.ny));
+    double rho_q[3] = {0.0, 0.0, 0.0};  // own rho at planes z, z+1, z+2
+
+    // Load plane zz into ring slot zz mod 5; when it is an output plane of
+    // this tile, fold its pointwise diagnostics. Returns own rho.
+    auto enter = [&](int zz) -> double {
+        const size_t po = (size_t)pmodi(zz, d.nz) * plane;
+        double* V = sV + pmodi(zz, kRing) * 3 * kNPL;
         double qv[5];
 #pragma unroll
-        for (int f = 0; f < 5; ++f) qv[f] = (double)q[f * n + e];
-        double nf = 0.0;
+        for (int f = 0; f < 5; ++f) qv[f] = (double)q[f * n + po + col];
+        const double ir = 1.0 / qv[0];
+        const double u = qv[1] * ir, v = qv[2] * ir, w = qv[3] * ir;
+        V[own] = u;
+        V[kNPL + own] = v;
+        V[2 * kNPL + own] = w;
+        if (hval) {
+            const double hr = (double)q[po + hcol];
+            const double hi = 1.0 / hr;
+            V[hidx] = (double)q[n + po + hcol] * hi;
+            V[kNPL + hidx] = (double)q[2 * n + po + hcol] * hi;
+            V[2 * kNPL + hidx] = (double)q[3 * n + po + hcol] * hi;
+        }
+        if (active && zz >= z0 && zz < z1) {
+            double nf = 0.0;
 #pragma unroll
-        for (int f = 0; f < 5; ++f) nf += isfinite(qv[f]) ? 0.0 : 1.0;
-        const double u = qv[1] / qv[0], v = qv[2] / qv[0], w = qv[3] / qv[0];
-        const double ke = 0.5 * qv[0] * (u * u + v * v + w * w);
-        const double p = gm1 * (qv[4] - ke);
-        // vorticity from the fourth-order first derivative of the velocity
-        double dvel[3][3];  // dvel[b][a] = D_b u_a
+            for (int f = 0; f < 5; ++f) nf += isfinite(qv[f]) ? 0.0 : 1.0;
+            const double ke = 0.5 * qv[0] * (u * u + v * v + w * w);
+            const double p = gm1 * (qv[4] - ke);
+            acc[0] += ke;
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            double vm2[3], vm1[3], vp1[3], vp2[3];
-            size_t em2, em1, ep1, ep2;
-            const size_t sx = 1, sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
-            const size_t base = e;
-            if (b == 0) {
-                const size_t row = e - i;
-                em2 = row + wrap(i - 2, d.nx); em1 = row + wrap(i - 1, d.nx);
-                ep1 = row + wrap(i + 1, d.nx); ep2 = row + wrap(i + 2, d.nx);
-            } else if (b == 1) {
-                const size_t pl = base - (size_t)j * sy;
-                em2 = pl + wrap(j - 2, d.ny) * sy; em1 = pl + wrap(j - 1, d.ny) * sy;
-                ep1 = pl + wrap(j + 1, d.ny) * sy; ep2 = pl + wrap(j + 2, d.ny) * sy;
-            } else {
-                const size_t col = base - (size_t)k * sz;
-                em2 = col + wrap(k - 2, d.nz) * sz; em1 = col + wrap(k - 1, d.nz) * sz;
-                ep1 = col + wrap(k + 1, d.nz) * sz; ep2 = col + wrap(k + 2, d.nz) * sz;
+            for (int f = 0; f < 5; ++f) {
+                acc[2 + f] += qv[f];
+                acc[7 + f] = fmax(acc[7 + f], fabs(qv[f]));
             }
-            (void)sx;
-            vel_at(q, n, em2, vm2);
-            vel_at(q, n, em1, vm1);
-            vel_at(q, n, ep1, vp1);
-            vel_at(q, n, ep2, vp2);
-            const double a1 = c.a1[b], a2 = c.a2[b];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) dvel[b][a] = a1 * (vp1[a] - vm1[a]) + a2 * (vp2[a] - vm2[a]);
+            acc[12] = fmin(acc[12], qv[0]);
+            acc[13] = fmin(acc[13], p);
+            acc[14] += nf;
+            acc[15] += p;
         }
-        const double ox = dvel[1][2] - dvel[2][1];
-        const double oy = dvel[2][0] - dvel[0][2];
-        const double oz = dvel[0][1] - dvel[1][0];
-        acc[0] += ke;
-        acc[1] += 0.5 * qv[0] * (ox * ox + oy * oy + oz * oz);
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            acc[2 + f] += qv[f];
-            acc[7 + f] = fmax(acc[7 + f], fabs(qv[f]));
-        }
-        acc[12] = fmin(acc[12], qv[0]);
-        acc[13] = fmin(acc[13], p);
-        acc[14] += nf;
-        acc[15] += p;
+        return qv[0];
+    };
+
+    for (int s = 0; s < 4; ++s) {
+        const double r = enter(z0 - 2 + s);
+        if (s >= 2) rho_q[s - 2] = r;
     }
-    block_reduce(acc);
+    const double a1x = A.c.a1[0], a2x = A.c.a2[0], a1y = A.c.a1[1], a2y = A.c.a2[1];
+    const double a1z = A.c.a1[2], a2z = A.c.a2[2];
+    for (int z = z0; z < z1; ++z) {
+        rho_q[2] = enter(z + 2);
+        __syncthreads();
+        if (active) {
+            const double* Vc = sV + pmodi(z, kRing) * 3 * kNPL;
+            double G[3][3];  // G[a][b] = D_b u_a
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double* F = Vc + a * kNPL;
+                G[a][0] = a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]);
+                G[a][1] = a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]);
+                const double* Fm2 = sV + pmodi(z - 2, kRing) * 3 * kNPL + a * kNPL;
+                const double* Fm1 = sV + pmodi(z - 1, kRing) * 3 * kNPL + a * kNPL;
+                const double* Fp1 = sV + pmodi(z + 1, kRing) * 3 * kNPL + a * kNPL;
+                const double* Fp2 = sV + pmodi(z + 2, kRing) * 3 * kNPL + a * kNPL;
+                G[a][2] = a1z * (Fp1[own] - Fm1[own]) + a2z * (Fp2[own] - Fm2[own]);
+            }
+            const double ox = G[2][1] - G[1][2];
+            const double oy = G[0][2] - G[2][0];
+            const double oz = G[1][0] - G[0][1];
+            acc[1] += 0.5 * rho_q[0] * (ox * ox + oy * oy + oz * oz);
+        }
+        rho_q[0] = rho_q[1];
+        rho_q[1] = rho_q[2];
+        __syncthreads();
+    }
+    block_reduce<kNT>(acc, sRed);
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int s = 0; s < kND; ++s) partial[(size_t)blockIdx.x * kND + s] = acc[s];
+        for (int s = 0; s < kND; ++s) partial[(size_t)t * kND + s] = acc[s];
 }
 
-__global__ void __launch_bounds__(kThreads) k_diag_final(int nblocks, double inv_n,
-                                                         const double* __restrict__ partial,
-                                                         double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_diag_final(int nblocks, double inv_n,
+                                                    const double* __restrict__ partial,
+                                                    double* __restrict__ out) {
+    __shared__ double sRed[4 * kND];
     double acc[kND];
 #pragma unroll
     for (int s = 0; s < kND; ++s) acc[s] = identity(s);
-    for (int b = threadIdx.x; b < nblocks; b += kThreads)
+    for (int b = threadIdx.x; b < nblocks; b += 256)
 #pragma unroll
         for (int s = 0; s < kND; ++s) acc[s] = combine(s, acc[s], partial[(size_t)b * kND + s]);
-    block_reduce(acc);
+    block_reduce<256>(acc, sRed);
     if (threadIdx.x == 0) {
         const int means[] = {0, 1, 2, 3, 4, 5, 6, 15};
         for (int m = 0; m < 8; ++m) acc[means[m]] *= inv_n;
@@ -155,24 +230,37 @@ __global__ void __launch_bounds__(kThreads) k_diag_final(int nblocks, double inv
     }
 }
 
-int nblocks_for(const Dims& d) {
-    size_t b = (d.npts + kThreads - 1) / kThreads;
-    if (b > (size_t)kMaxBlocks) b = kMaxBlocks;
-    return (int)(b < 1 ? 1 : b);
+int diag_zchunk(const Dims& d) { return d.nz >= 64 ? 64 : d.nz; }
+
+void diag_tiles(const Dims& d, int* tx, int* ty, int* tz) {
+    *tx = (d.nx + kTX - 1) / kTX;
+    *ty = (d.ny + kTY - 1) / kTY;
+    const int zc = diag_zchunk(d);
+    *tz = (d.nz + zc - 1) / zc;
 }
 
 }  // namespace
 
-size_t diag_partial_count(const Dims& d) { return (size_t)nblocks_for(d); }
+size_t diag_partial_count(const Dims& d) {
+    int tx, ty, tz;
+    diag_tiles(d, &tx, &ty, &tz);
+    return (size_t)tx * ty * tz;
+}
 
 template <typename T>
 void launch_diag(const Dims& d, const Coef<double>& c, const T* q, double* partial, double* out_dev,
                  hipStream_t s) {
     TimerScope ts("diag", s);
-    const int nb = nblocks_for(d);
-    hipLaunchKernelGGL(k_diag_partial<T>, dim3(nb), dim3(kThreads), 0, s, d, c, q, partial);
-    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kThreads), 0, s, nb, 1.0 / (double)d.npts,
-                       partial, out_dev);
+    DiagArgs a;
+    a.d = d;
+    a.c = c;
+    a.zchunk = diag_zchunk(d);
+    int tz;
+    diag_tiles(d, &a.tiles_x, &a.tiles_y, &tz);
+    const int nb = a.tiles_x * a.tiles_y * tz;
+    hipLaunchKernelGGL(k_diag_partial<T>, dim3(nb), dim3(kNT), 0, s, a, q, partial);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, nb, 1.0 / (double)d.npts, partial,
+                       out_dev);
 }
 
 template void launch_diag<float>(const Dims&, const Coef<double>&, const float*, double*, double*,

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/nsf.h"
 #include "nsf_device.h"
 
 namespace nsf {
@@ -24,6 +25,9 @@ struct StageCoef {
 
 // Record an error message for nsf_last_error() and return `code`.
 int set_error(int code, const char* msg);
+
+// Autotuner table (nsf_tune.cpp): the recorded algorithm and tuning.
+bool tune_lookup(const Dims& d, int precision, int* variant, nsf_tuning* tune);
 
 // Launch-time kernel timer (nsf_timer_*): brackets launches of the enabled
 // kernel family with HIP events on the launch stream.
@@ -77,6 +81,7 @@ struct ZArgs {
     Coef<T> k;
     const T* q;
     const T* prim;
+    const T* grad;  // stored velocity gradients (SS), G_ab at field 3a + b
     T* r;
     T* qout;
     double* qacc;
@@ -113,6 +118,14 @@ int batch_blocks_per_cu(int tile_y);
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
                       int zchunk, int tile_y, hipStream_t s);
+// SS residual: the tiled sweep with the velocity gradients and D_a(G_cc)
+// read from the nine stored gradient arrays.
+template <typename T>
+void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
+                      T* r, int zchunk, int tile_y, hipStream_t s);
+// SS gradient loop: G_ab = D_b u_a into nine arrays (z-marching tiles).
+template <typename T>
+void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hipStream_t s);
 // Fused RA stage: primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),
 // q_acc += B dt R. qout must not alias q.

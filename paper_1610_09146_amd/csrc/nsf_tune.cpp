@@ -1,0 +1,315 @@
+// Autotuner: searches the paper's store-versus-recompute trade-off (which
+// algorithm: BL, RA with stored or recomputed primitives, SS) together with
+// the implementation knobs of the z-sweeping kernels (tile height, z-chunk)
+// for one grid and precision. Every candidate must first reproduce the
+// untiled reference residual on a seeded, symmetry-broken Taylor-Green state
+// of the same grid; only candidates that pass are timed. The winner is kept
+// in a process-wide table consulted by the NSF_AUTO algorithm value and can
+// be appended to a JSON-lines cache file.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/nsf.h"
+#include "nsf_internal.h"
+
+using namespace nsf;
+
+namespace {
+
+struct Entry {
+    int nx, ny, nz, precision;
+    nsf_tune_result r;
+};
+
+std::mutex g_mu;
+std::vector<Entry> g_table;
+
+int tfail(int code, const char* msg) { return set_error(code, msg); }
+
+// max over points of |a - b| and of |b|, per field, on the device
+__global__ void k_maxdiff(size_t n, const void* a, const void* b, int is_f32, double* out) {
+    __shared__ double sd[256], sr[256];
+    double md = 0.0, mr = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const double x = is_f32 ? (double)((const float*)a)[e] : ((const double*)a)[e];
+        const double y = is_f32 ? (double)((const float*)b)[e] : ((const double*)b)[e];
+        const double dd = fabs(x - y);
+        md = (dd > md || dd != dd) ? dd : md;  // a NaN difference propagates
+        mr = fmax(mr, fabs(y));
+    }
+    sd[threadIdx.x] = md;
+    sr[threadIdx.x] = mr;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = sd[threadIdx.x + w];
+            sd[threadIdx.x] = (o > sd[threadIdx.x] || o != o) ? o : sd[threadIdx.x];
+            sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = sd[0];
+        out[2 * blockIdx.x + 1] = sr[0];
+    }
+}
+
+constexpr int kDiffBlocks = 512;
+
+// Relative max-norm difference per field, worst field returned.
+int rel_diff(const Dims& d, int precision, const void* a, const void* b, double* partial,
+             hipStream_t s, double* worst) {
+    const size_t es = precision == NSF_F32 ? 4 : 8;
+    std::vector<double> host(2 * kDiffBlocks);
+    double w = 0.0;
+    for (int f = 0; f < 5; ++f) {
+        const char* pa = (const char*)a + f * d.npts * es;
+        const char* pb = (const char*)b + f * d.npts * es;
+        hipLaunchKernelGGL(k_maxdiff, dim3(kDiffBlocks), dim3(256), 0, s, d.npts, pa, pb,
+                           precision == NSF_F32, partial);
+        hipError_t e = hipMemcpyAsync(host.data(), partial, host.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return tfail(NSF_EHIP, hipGetErrorString(e));
+        double md = 0.0, mr = 0.0;
+        for (int i = 0; i < kDiffBlocks; ++i) {
+            const double x = host[2 * i];
+            md = (x > md || x != x) ? x : md;
+            mr = std::max(mr, host[2 * i + 1]);
+        }
+        const double rel = mr > 0 ? md / mr : md;
+        w = (rel > w || rel != rel) ? rel : w;
+    }
+    *worst = w;
+    return NSF_OK;
+}
+
+std::vector<nsf_tune_result> candidates(const nsf_grid* g, int flags) {
+    std::vector<nsf_tune_result> c;
+    auto add = [&](int variant, int by, int zc, int fuse, int naive) {
+        nsf_tune_result r;
+        std::memset(&r, 0, sizeof r);
+        r.variant = variant;
+        r.tune.block_x = 32;
+        r.tune.block_y = by;
+        r.tune.zchunk = zc;
+        r.tune.fuse = fuse;
+        r.tune.naive = naive;
+        c.push_back(r);
+    };
+    std::vector<int> zcs;
+    for (int zc : {16, 32, 64, 128})
+        if (zc <= g->nz) zcs.push_back(zc);
+    if (zcs.empty()) zcs.push_back(g->nz);
+    for (int by : {8, 16}) {
+        for (int zc : zcs) add(NSF_RA, by, zc, 1, 0);
+        add(NSF_RA, by, zcs.back() >= 64 ? 64 : zcs.back(), 0, 0);
+        add(NSF_SS, by, zcs.back() >= 64 ? 64 : zcs.back(), 0, 0);
+    }
+    if (!(flags & NSF_TUNE_QUICK)) {
+        add(NSF_BL, 0, 0, 0, 0);
+        add(NSF_RA, 0, 0, 0, 1);
+        add(NSF_SS, 0, 0, 0, 1);
+    }
+    return c;
+}
+
+int append_cache(const char* path, const nsf_grid* g, int precision, const nsf_tune_result& r) {
+    FILE* f = std::fopen(path, "a");
+    if (!f) return tfail(NSF_EINVAL, "autotune: cannot open cache file");
+    std::fprintf(f,
+                 "{\"arch\": \"gfx950\", \"nx\": %d, \"ny\": %d, \"nz\": %d, \"precision\": %d, "
+                 "\"variant\": %d, \"block_x\": %d, \"block_y\": %d, \"zchunk\": %d, \"fuse\": %d, "
+                 "\"naive\": %d, \"pt_rhs_per_s\": %.6e, \"parity_rel_err\": %.3e}\n",
+                 g->nx, g->ny, g->nz, precision, r.variant, r.tune.block_x, r.tune.block_y,
+                 r.tune.zchunk, r.tune.fuse, r.tune.naive, r.pt_rhs_per_s, r.parity_rel_err);
+    std::fclose(f);
+    return NSF_OK;
+}
+
+bool get_int(const char* line, const char* key, int* v) {
+    char pat[64];
+    std::snprintf(pat, sizeof pat, "\"%s\":", key);
+    const char* p = std::strstr(line, pat);
+    if (!p) return false;
+    return std::sscanf(p + std::strlen(pat), " %d", v) == 1;
+}
+
+bool get_double(const char* line, const char* key, double* v) {
+    char pat[64];
+    std::snprintf(pat, sizeof pat, "\"%s\":", key);
+    const char* p = std::strstr(line, pat);
+    if (!p) return false;
+    return std::sscanf(p + std::strlen(pat), " %lf", v) == 1;
+}
+
+void remember(const nsf_grid* g, int precision, const nsf_tune_result& r) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (Entry& e : g_table)
+        if (e.nx == g->nx && e.ny == g->ny && e.nz == g->nz && e.precision == precision) {
+            e.r = r;
+            return;
+        }
+    g_table.push_back(Entry{g->nx, g->ny, g->nz, precision, r});
+}
+
+}  // namespace
+
+namespace nsf {
+bool tune_lookup(const Dims& d, int precision, int* variant, nsf_tuning* tune) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Entry& e : g_table)
+        if (e.nx == d.nx && e.ny == d.ny && e.nz == d.nz && e.precision == precision) {
+            *variant = e.r.variant;
+            *tune = e.r.tune;
+            return true;
+        }
+    return false;
+}
+}  // namespace nsf
+
+extern "C" {
+
+int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int flags, int32_t steps,
+                 const char* cache_path, nsf_tune_result* best, void* stream) {
+    if (!g || !phys || !best) return tfail(NSF_EINVAL, "autotune: NULL argument");
+    if (precision != NSF_F64 && precision != NSF_F32) return tfail(NSF_EINVAL, "autotune: precision");
+    size_t tmp = 0;
+    int rc = nsf_workspace_bytes(g, NSF_RA, precision, nullptr, &tmp);
+    if (rc) return rc;
+    if (steps < 1) steps = 2;
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d{g->nx, g->ny, g->nz, (size_t)g->nx * g->ny * g->nz};
+    const size_t es = precision == NSF_F32 ? 4 : 8;
+    const size_t fb = 5 * d.npts * es, ab = 5 * d.npts * sizeof(double);
+    std::vector<nsf_tune_result> cands = candidates(g, flags);
+    size_t wmax = 0;
+    for (auto& c : cands) {
+        size_t w = 0;
+        if ((rc = nsf_workspace_bytes(g, c.variant, precision, &c.tune, &w))) return rc;
+        wmax = std::max(wmax, w);
+    }
+    // buffers: initial state, working state, accumulator, residual (x2), work
+    void *q0 = nullptr, *q = nullptr, *r = nullptr, *rref = nullptr, *work = nullptr;
+    double *qacc = nullptr, *partial = nullptr;
+    hipError_t e = hipMalloc(&q0, fb);
+    if (e == hipSuccess) e = hipMalloc(&q, fb);
+    if (e == hipSuccess) e = hipMalloc(&r, fb);
+    if (e == hipSuccess) e = hipMalloc(&rref, fb);
+    if (e == hipSuccess) e = hipMalloc((void**)&qacc, ab);
+    if (e == hipSuccess) e = hipMalloc(&work, wmax);
+    if (e == hipSuccess) e = hipMalloc((void**)&partial, 2 * kDiffBlocks * sizeof(double));
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    auto cleanup = [&]() {
+        for (void* p : {q0, q, r, rref, work, (void*)qacc, (void*)partial})
+            if (p) (void)hipFree(p);
+        if (t0) (void)hipEventDestroy(t0);
+        if (t1) (void)hipEventDestroy(t1);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        return tfail(NSF_EHIP, hipGetErrorString(e));
+    }
+    // seeded, symmetry-broken Taylor-Green state (pointwise velocity noise)
+    nsf_tgv tgv;
+    std::memset(&tgv, 0, sizeof tgv);
+    tgv.V0 = 1.0;
+    tgv.pert_kind = 1;
+    tgv.pert_amp = 1e-2;
+    tgv.seed = 0x9146;
+    if ((rc = nsf_init_fields(g, phys, &tgv, precision, q0, qacc, stream))) { cleanup(); return rc; }
+    // reference residual: the untiled per-point RA kernels
+    nsf_tuning ref;
+    std::memset(&ref, 0, sizeof ref);
+    ref.naive = 1;
+    if ((rc = nsf_rhs(g, phys, NSF_RA, precision, &ref, q0, rref, work, wmax, stream))) { cleanup(); return rc; }
+    const double bar = precision == NSF_F64 ? 1e-10 : 1e-3;
+    const double dt = 1e-4;
+    nsf_tune_result win;
+    std::memset(&win, 0, sizeof win);
+    win.variant = -1;
+    for (auto& c : cands) {
+        // parity gate
+        if ((rc = nsf_rhs(g, phys, c.variant, precision, &c.tune, q0, r, work, wmax, stream))) break;
+        double err = 0.0;
+        if ((rc = rel_diff(d, precision, r, rref, partial, s, &err))) break;
+        c.parity_rel_err = err;
+        if (!(err <= bar)) {
+            c.pt_rhs_per_s = 0.0;
+            continue;
+        }
+        // timing: one untimed step, then `steps` steps between events
+        e = hipMemcpyAsync(q, q0, fb, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) { rc = tfail(NSF_EHIP, hipGetErrorString(e)); break; }
+        if ((rc = nsf_rk_step(g, phys, c.variant, precision, &c.tune, dt, 1, q, qacc, r, work, wmax, stream))) break;
+        e = hipEventRecord(t0, s);
+        if (e == hipSuccess &&
+            (rc = nsf_rk_step(g, phys, c.variant, precision, &c.tune, dt, steps, q, qacc, r, work, wmax, stream)))
+            break;
+        if (e == hipSuccess) e = hipEventRecord(t1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(t1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+        if (e != hipSuccess) { rc = tfail(NSF_EHIP, hipGetErrorString(e)); break; }
+        c.pt_rhs_per_s = (double)d.npts * 3.0 * steps / (ms * 1e-3);
+        if (c.pt_rhs_per_s > win.pt_rhs_per_s) win = c;
+    }
+    cleanup();
+    if (rc) return rc;
+    if (win.variant < 0) return tfail(NSF_EUNSUPPORTED, "autotune: no candidate passed the parity gate");
+    *best = win;
+    remember(g, precision, win);
+    if (cache_path && *cache_path) return append_cache(cache_path, g, precision, win);
+    return NSF_OK;
+}
+
+int nsf_tune_load(const char* cache_path) {
+    if (!cache_path) return tfail(NSF_EINVAL, "tune_load: NULL path");
+    FILE* f = std::fopen(cache_path, "r");
+    if (!f) return tfail(NSF_EINVAL, "tune_load: cannot open cache file");
+    char line[1024];
+    int loaded = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        if (!std::strstr(line, "\"gfx950\"")) continue;
+        nsf_grid g;
+        int precision = 0;
+        nsf_tune_result r;
+        std::memset(&r, 0, sizeof r);
+        if (!get_int(line, "nx", &g.nx) || !get_int(line, "ny", &g.ny) || !get_int(line, "nz", &g.nz) ||
+            !get_int(line, "precision", &precision) || !get_int(line, "variant", &r.variant))
+            continue;
+        get_int(line, "block_x", &r.tune.block_x);
+        get_int(line, "block_y", &r.tune.block_y);
+        get_int(line, "zchunk", &r.tune.zchunk);
+        get_int(line, "fuse", &r.tune.fuse);
+        get_int(line, "naive", &r.tune.naive);
+        get_double(line, "pt_rhs_per_s", &r.pt_rhs_per_s);
+        get_double(line, "parity_rel_err", &r.parity_rel_err);
+        remember(&g, precision, r);  // later lines override earlier ones
+        ++loaded;
+    }
+    std::fclose(f);
+    return loaded;
+}
+
+int nsf_tune_get(const nsf_grid* g, int precision, nsf_tune_result* out) {
+    if (!g || !out) return tfail(NSF_EINVAL, "tune_get: NULL argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Entry& e : g_table)
+        if (e.nx == g->nx && e.ny == g->ny && e.nz == g->nz && e.precision == precision) {
+            *out = e.r;
+            return NSF_OK;
+        }
+    return tfail(NSF_EUNSUPPORTED, "tune_get: no entry for this grid and precision");
+}
+
+}  // extern "C"

@@ -271,9 +271,10 @@ constexpr int kRing = 5;
 // every halo point is fetched once per plane, in the same iteration in
 // which the neighbouring tile fetches it as interior). Ends with a
 // barrier, so the caller may reuse the LDS for another tile right away.
-template <typename T, int TX, int TY, bool FUSED>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
                                             T* __restrict__ sV, T* __restrict__ sH) {
+    static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -310,6 +311,16 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     }
     auto poff = [&](int z) { return (size_t)pmod(z, d.nz) * plane; };
     auto ring = [&](int z) { return sV + pmod(z, RING) * 3 * NPL; };
+    // in-plane offsets of the own column's x and y neighbours at -2, -1, +1, +2
+    size_t xnb[4], ynb[4];
+    if constexpr (SS) {
+        const int ms[4] = {-2, -1, 1, 2};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            xnb[m] = (size_t)pmod(gj, d.ny) * d.nx + pmod(gi + ms[m], d.nx);
+            ynb[m] = (size_t)pmod(gj + ms[m], d.ny) * d.nx + pmod(gi, d.nx);
+        }
+    }
 
     // register queue of the own column, planes z-2 .. z+2 (velocity in the ring)
     Pt<T> Qz[5];
@@ -372,7 +383,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 V[2 * NPL + hidx[h]] = w;
             }
         __syncthreads();
-        leading(V, Xs[s], Xw[s], Yw[s]);
+        if constexpr (!SS) leading(V, Xs[s], Xw[s], Yw[s]);
     }
 
     // prefetched halo values for the first iteration: fused form, raw q of
@@ -450,7 +461,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         __syncthreads();
 
         // (c) leading-plane in-plane derivatives for the z cross terms
-        leading(Vl, Xs[4], Xw[4], Yw[4]);
+        if constexpr (!SS) leading(Vl, Xs[4], Xw[4], Yw[4]);
 
         // (d) residual at plane z
         const T* Vc = ring(z);
@@ -515,7 +526,33 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         }
         // cross derivatives sum_{c != a} D_a(G_cc)
         T cross[3];
-        {
+        if constexpr (SS) {
+            // stored velocity gradients (G_ab at 3a + b): pointwise values
+            // for the assembly, and D_a of the stored diagonal G_cc
+            const T* Gs = A.grad;
+            const size_t pz = poff(z);
+            auto gat = [&](int comp, size_t off) { return Gs[comp * n + off]; };
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) ac.G[a][b] = gat(3 * a + b, pz + col);
+            auto dxg = [&](int comp) {
+                return D1(gat(comp, pz + xnb[0]), gat(comp, pz + xnb[1]), gat(comp, pz + xnb[2]),
+                          gat(comp, pz + xnb[3]), k.a1[0], k.a2[0]);
+            };
+            auto dyg = [&](int comp) {
+                return D1(gat(comp, pz + ynb[0]), gat(comp, pz + ynb[1]), gat(comp, pz + ynb[2]),
+                          gat(comp, pz + ynb[3]), k.a1[1], k.a2[1]);
+            };
+            auto dzg = [&](int comp) {
+                return D1(gat(comp, poff(z - 2) + col), gat(comp, poff(z - 1) + col),
+                          gat(comp, poff(z + 1) + col), gat(comp, poff(z + 2) + col), k.a1[2],
+                          k.a2[2]);
+            };
+            cross[0] = dxg(4) + dxg(8);
+            cross[1] = dyg(0) + dyg(8);
+            cross[2] = dzg(0) + dzg(4);
+        } else {
             const T* U = Vc;
             const T* Vv = Vc + NPL;
             auto dyv = [&](int mx) {
@@ -576,7 +613,7 @@ struct Occ {
     static constexpr int kWaves = sizeof(T) == 8 ? 2 : 3;
 };
 
-template <typename T, int TX, int TY, bool FUSED>
+template <typename T, int TX, int TY, bool FUSED, bool SS>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
@@ -584,7 +621,7 @@ k_ra_zsweep(ZArgs<T> A) {
     __shared__ T sP[7 * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
     __shared__ T sH[FUSED ? 15 * G::NHALO : 1];
-    zsweep_tile<T, TX, TY, FUSED>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH);
+    zsweep_tile<T, TX, TY, FUSED, SS>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH);
 }
 
 // Persistent batched stage kernel: every workgroup walks the work list of
@@ -615,6 +652,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.q = stage == 0 ? bd.q : (stage == 1 ? bd.qb : bd.qc);
         A.qout = stage == 0 ? bd.qb : (stage == 1 ? bd.qc : bd.q);
         A.prim = nullptr;
+        A.grad = nullptr;
         A.r = nullptr;
         A.qacc = bd.qacc;
         A.a_dt = stage < 2 ? A_[stage] * bd.dt : 0.0;
@@ -627,7 +665,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
     }
 }
 
-template <typename T, int TX, int TY, bool FUSED>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false>
 void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     ZArgs<T> a = a0;
     const Dims& d = a.d;
@@ -636,7 +674,7 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     a.tiles_y = (d.ny + TY - 1) / TY;
     const int tiles_z = (d.nz + a.zchunk - 1) / a.zchunk;
     const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * tiles_z);
-    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED>), dim3(nb), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS>), dim3(nb), dim3(TX * TY), 0, s, a);
 }
 
 }  // namespace
@@ -670,6 +708,21 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.r = r;
     if (tile_y == 16) launch_tiles<T, kTX, 16, false>(a, zchunk, s);
     else launch_tiles<T, kTX, 8, false>(a, zchunk, s);
+}
+
+template <typename T>
+void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
+                      T* r, int zchunk, int tile_y, hipStream_t s) {
+    TimerScope ts("ss_zsweep", s);
+    ZArgs<T> a{};
+    a.d = d;
+    a.k = c;
+    a.q = q;
+    a.prim = prim;
+    a.grad = grad;
+    a.r = r;
+    if (tile_y == 16) launch_tiles<T, kTX, 16, false, true>(a, zchunk, s);
+    else launch_tiles<T, kTX, 8, false, true>(a, zchunk, s);
 }
 
 template <typename T>
@@ -716,6 +769,8 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     template int batch_blocks_per_cu<T>(int);                                                 \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
                                       int, int, hipStream_t);                               \
+    template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
+                                      const T*, T*, int, int, hipStream_t);                 \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
                                      const StageCoef&, int, int, hipStream_t);
 NSF_INST(float)

@@ -21,10 +21,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnsf.so")
 
 OK, EINVAL, EWORKSPACE, EHIP, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
-BL, RA, SS, SN, RS = 0, 1, 2, 3, 4
+BL, RA, SS, SN, RS, AUTO = 0, 1, 2, 3, 4, 5
 F64, F32 = 0, 1
 NDIAG = 16
-VARIANTS = {"BL": BL, "RA": RA, "SS": SS, "SN": SN, "RS": RS}
+TUNE_QUICK = 1
+VARIANTS = {"BL": BL, "RA": RA, "SS": SS, "SN": SN, "RS": RS, "AUTO": AUTO}
+VARIANT_NAMES = {v: k for k, v in VARIANTS.items()}
 PRECISIONS = {"f64": F64, "f32": F32}
 DIAG_NAMES = [
     "ke", "enstrophy", "mean_rho", "mean_rhou", "mean_rhov", "mean_rhow", "mean_rhoE",
@@ -58,6 +60,11 @@ class Tuning(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("fuse", ctypes.c_int32), ("naive", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 3)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("tune", Tuning), ("pt_rhs_per_s", ctypes.c_double),
+                ("parity_rel_err", ctypes.c_double)]
 
 
 _lib = None
@@ -96,6 +103,13 @@ def lib() -> ctypes.CDLL:
         L.nsf_batch_diagnostics.argtypes = [vp, ctypes.POINTER(d), vp]
         L.nsf_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.nsf_batch_destroy.argtypes = [vp]
+        L.nsf_batch_create_tuned.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, Tu,
+                                             ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
+                                             ctypes.POINTER(vp)]
+        TR = ctypes.POINTER(TuneResult)
+        L.nsf_autotune.argtypes = [G, P, ctypes.c_int, ctypes.c_int, i32, ctypes.c_char_p, TR, vp]
+        L.nsf_tune_load.argtypes = [ctypes.c_char_p]
+        L.nsf_tune_get.argtypes = [G, ctypes.c_int, TR]
         _lib = L
     return _lib
 
@@ -204,6 +218,39 @@ def diagnostics(shape, phys, precision, q, work, stream=None, check: bool = True
     if check or rc != ENONFINITE:
         _check(rc, "nsf_diagnostics")
     return np.array(out[:], dtype=np.float64)
+
+
+def _tune_dict(r: TuneResult) -> dict:
+    t = r.tune
+    return {"variant": VARIANT_NAMES.get(int(r.variant), int(r.variant)),
+            "tune": {"block_x": t.block_x, "block_y": t.block_y, "zchunk": t.zchunk,
+                     "fuse": t.fuse, "naive": t.naive},
+            "pt_rhs_per_s": float(r.pt_rhs_per_s), "parity_rel_err": float(r.parity_rel_err)}
+
+
+def autotune(shape, phys, precision, quick: bool = True, steps: int = 2,
+             cache_path: str | None = None, stream=None) -> dict:
+    """Run the autotuner for one grid and precision (synchronous); the choice
+    is recorded for variant "AUTO" in this process."""
+    r = TuneResult()
+    _check(lib().nsf_autotune(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                              _precision(precision), TUNE_QUICK if quick else 0, int(steps),
+                              cache_path.encode() if cache_path else None, ctypes.byref(r),
+                              _stream(stream)), "nsf_autotune")
+    return _tune_dict(r)
+
+
+def tune_load(cache_path: str) -> int:
+    rc = lib().nsf_tune_load(cache_path.encode())
+    if rc < 0:
+        _check(rc, "nsf_tune_load")
+    return int(rc)
+
+
+def tune_get(shape, precision) -> dict | None:
+    r = TuneResult()
+    rc = lib().nsf_tune_get(ctypes.byref(_grid(shape)), _precision(precision), ctypes.byref(r))
+    return _tune_dict(r) if rc == OK else None
 
 
 def device_copy(src: torch.Tensor, dst: torch.Tensor, nbytes: int | None = None, stream=None) -> None:
