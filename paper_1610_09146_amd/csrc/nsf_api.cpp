@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nsf.h"
+#include "nsf.h"
 #include "nsf_internal.h"
 
 namespace nsf {

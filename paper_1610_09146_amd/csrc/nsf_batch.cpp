@@ -8,7 +8,7 @@
 #include <cstring>
 #include <vector>
 
-#include "../../include/nsf.h"
+#include "nsf.h"
 #include "nsf_internal.h"
 
 using namespace nsf;

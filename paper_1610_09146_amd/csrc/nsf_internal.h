@@ -4,7 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
-#include "../../include/nsf.h"
+#include "nsf.h"
 #include "nsf_device.h"
 
 namespace nsf {

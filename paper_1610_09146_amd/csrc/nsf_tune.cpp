@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/nsf.h"
+#include "nsf.h"
 #include "nsf_internal.h"
 
 using namespace nsf;

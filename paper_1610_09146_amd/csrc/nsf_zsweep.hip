@@ -458,6 +458,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
                 }
             }
+        // fused form: the accumulator of plane z. In single precision it is
+        // fetched here, before the compute, so its latency is covered; in
+        // double precision the registers are not there (the spill costs more
+        // than the exposed latency) and it is fetched in the epilogue.
+        constexpr bool kEarlyAcc = FUSED && sizeof(T) == 4;
+        const size_t oidx = (size_t)z * plane + col;
+        double acc[FUSED ? 5 : 1];
+        if constexpr (kEarlyAcc) {
+#pragma unroll
+            for (int f = 0; f < 5; ++f) acc[f] = active ? A.qacc[f * n + oidx] : 0.0;
+        }
         __syncthreads();
 
         // (c) leading-plane in-plane derivatives for the z cross terms
@@ -575,12 +586,12 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             const T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
             finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R);
         }
-        const size_t oidx = (size_t)z * plane + col;
         if (active) {
-            if (FUSED) {
-                double acc[5];
+            if constexpr (FUSED) {
+                if constexpr (!kEarlyAcc) {
 #pragma unroll
-                for (int f = 0; f < 5; ++f) acc[f] = A.qacc[f * n + oidx];
+                    for (int f = 0; f < 5; ++f) acc[f] = A.qacc[f * n + oidx];
+                }
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     const double rr = (double)R[f];
