@@ -174,6 +174,58 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     return out
 
 
+def precision_errors(nsf, torch, W, n, steps, tuned):
+    """FP32 form against the parity-checked FP64 GPU run (proxy for the FP64
+    oracle at this size) after `steps` steps: relative errors of KE,
+    enstrophy, the KE change over the run, and per-field max-norms."""
+    out = {}
+    for prec in ("f64", "f32"):
+        var = tuned[prec]["variant"] if tuned else "RA"
+        tune = tuned[prec]["tune"] if tuned else {"fuse": 1}
+        s = nsf.Solver((n, n, n), W.TGV_PHYS, var, prec, tune=tune)
+        s.init(W.tgv_unperturbed())
+        s.step(W.tgv_dt(n), steps)
+        d = s.diagnostics()
+        out[prec] = (d, s.q_acc.abs().amax(dim=(1, 2, 3)).cpu().numpy(),
+                     s.q_acc.clone() if prec == "f64" else s.q_acc)
+        if prec == "f32":
+            diff = (s.q_acc - out["f64"][2]).abs().amax(dim=(1, 2, 3)).cpu().numpy()
+        del s
+    d64, d32 = out["f64"][0], out["f32"][0]
+    del out
+    torch.cuda.empty_cache()
+    return {"n": n, "steps": steps, "reference": "FP64 GPU run (parity-checked path)",
+            "ke_rel_err": abs(d32[0] - d64[0]) / abs(d64[0]),
+            "enstrophy_rel_err": abs(d32[1] - d64[1]) / abs(d64[1]),
+            "dke_rel_err": abs((d32[0] - 0.125) - (d64[0] - 0.125)) / abs(d64[0] - 0.125),
+            "maxnorm_rel_err": [float(x) for x in diff / out_max(d64)],
+            "ke_f64": float(d64[0]), "ke_f32": float(d32[0])}
+
+
+def out_max(d):
+    """Per-field max norms from a diagnostics vector."""
+    import numpy as np
+    return np.asarray(d[7:12])
+
+
+def batch_precision_errors(nsf, torch, W, steps):
+    """Batched FP32 form against the batched FP64 form, per instance, after
+    `steps` steps: largest relative KE error over the 64 instances."""
+    import numpy as np
+    insts = W.batch_instances()
+    ke = {}
+    for prec in ("f64", "f32"):
+        b = nsf.Batch(insts, prec)
+        b.step(steps)
+        ke[prec] = b.diagnostics()[:, 0]
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    rel = np.abs(ke["f32"] - ke["f64"]) / np.abs(ke["f64"])
+    return {"steps": steps, "instances": len(insts), "ke_rel_err_max": float(rel.max()),
+            "ke_rel_err_median": float(np.median(rel))}
+
+
 def roofline_of(res, precision):
     fam = res["dominant"]
     if not fam or res["dominant_launches"] == 0:
@@ -272,6 +324,9 @@ def main() -> int:
         for prec in ("f64", "f32"):
             log(f"extra: batch64 {prec}")
             extras[f"batch64_{prec}"] = run_batch(nsf, torch, W, prec, 10)
+        log("extra: FP32-form errors after 100 steps (512^3 and batch)")
+        extras["f32_errors_512_100steps"] = precision_errors(nsf, torch, W, n, 100, tuned)
+        extras["f32_errors_batch64_100steps"] = batch_precision_errors(nsf, torch, W, 100)
     line = {
         "metric": METRIC,
         "value": main_res["pt_rhs_per_s"],

@@ -334,7 +334,16 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     T unew[3] = {uvw[4][0], uvw[4][1], uvw[4][2]};  // own velocity of plane z+2
 
     // queued in-plane derivatives for the z cross terms: Dx u + Dy v, Dx w, Dy w
+    // (stored-gradient form: Xs and Xw queue the stored G_xx and G_yy of the
+    // own column instead, for D_z of the diagonal gradients)
     T Xs[5], Xw[5], Yw[5];
+    if constexpr (SS) {
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            Xs[s] = A.grad[0 * n + poff(z0 - 2 + s) + col];
+            Xw[s] = A.grad[4 * n + poff(z0 - 2 + s) + col];
+        }
+    }
     auto leading = [&](const T* V, T& s, T& xw, T& yw) {
         const T* U = V;
         const T* Vv = V + NPL;
@@ -448,6 +457,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // (b) prefetch the next iteration's loads
         Raw<T, FUSED> nxt;
         load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+        T gnx[SS ? 2 : 1];
+        if constexpr (SS) {
+            gnx[0] = A.grad[0 * n + poff(z + 3) + col];
+            gnx[1] = A.grad[4 * n + poff(z + 3) + col];
+        }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
@@ -555,14 +569,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 return D1(gat(comp, pz + ynb[0]), gat(comp, pz + ynb[1]), gat(comp, pz + ynb[2]),
                           gat(comp, pz + ynb[3]), k.a1[1], k.a2[1]);
             };
-            auto dzg = [&](int comp) {
-                return D1(gat(comp, poff(z - 2) + col), gat(comp, poff(z - 1) + col),
-                          gat(comp, poff(z + 1) + col), gat(comp, poff(z + 2) + col), k.a1[2],
-                          k.a2[2]);
-            };
             cross[0] = dxg(4) + dxg(8);
             cross[1] = dyg(0) + dyg(8);
-            cross[2] = dzg(0) + dzg(4);
+            cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], k.a1[2], k.a2[2]) +
+                       D1(Xw[0], Xw[1], Xw[3], Xw[4], k.a1[2], k.a2[2]);
         } else {
             const T* U = Vc;
             const T* Vv = Vc + NPL;
@@ -614,6 +624,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Yw[s] = Yw[s + 1];
         }
         Qz[4] = finish<T, FUSED>(nxt, k, unew);
+        if constexpr (SS) {
+            Xs[4] = gnx[0];
+            Xw[4] = gnx[1];
+        }
     }
 }
 

@@ -295,3 +295,28 @@ def test_rk_f32_form_against_f64_oracle():
         assert np.all(err[[0, 1, 2, 4]] <= 1e-6), err
         d = s.diagnostics()
         assert abs(d[0] - ref_d[0]) <= 1e-6 * ref_d[0]
+
+
+def test_f32_form_100_steps_against_f64_oracle():
+    # precision form: after 100 steps at 64^3 the kinetic energy of the FP32
+    # form (FP64 accumulator) is within 1e-5 relative of the FP64 oracle;
+    # the FP64 GPU path stays within 1e-10 of it
+    print("case f32_100_steps", flush=True)
+    n = 64
+    shape, dt, steps = (n, n, n), W.tgv_dt(n), 100
+    q0 = O.init(shape, PHYS, W.tgv_unperturbed(), prec="d")
+    ref = O.rk_step(q0, PHYS, dt, steps, prec="d")
+    dref = O.diagnostics(ref, PHYS)
+    out = {}
+    for prec in ("f64", "f32"):
+        s = nsf.Solver(shape, PHYS, "AUTO", prec)
+        s.init(W.tgv_unperturbed())
+        s.step(dt, steps)
+        out[prec] = (s.q_acc.cpu().numpy(), s.diagnostics())
+    assert np.all(rel_err(out["f64"][0], ref) <= 1e-10)
+    ke32, ens32 = out["f32"][1][0], out["f32"][1][1]
+    assert abs(ke32 - dref[0]) <= 1e-5 * dref[0], (ke32, dref[0])
+    assert abs(ens32 - dref[1]) <= 1e-4 * dref[1], (ens32, dref[1])
+    # the change of KE over the run is resolved too
+    dke_ref = dref[0] - 0.125
+    assert abs((ke32 - 0.125) - dke_ref) <= 2e-2 * abs(dke_ref)
