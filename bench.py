@@ -40,6 +40,7 @@ FAMILY_BYTES = {
     "ra_naive": (120, 60),        # q, prims -> r
     "ra_zsweep": (120, 60),       # q, prims -> r
     "ra_fused": (160, 120),       # q, q_acc -> q_next, q_acc
+    "ra_fused_mon": (160, 120),   # the same, plus per-tile KE / enstrophy sums
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
     "ss_grad": (96, 48),          # u, v, w -> 9 gradients
@@ -89,7 +90,7 @@ def families(variant, tune):
         return ["prims", "bl_product", "bl_deriv", "bl_assemble", "update", "diag"]
     if variant in ("RA", "SN"):
         if tune and tune.get("fuse"):
-            return ["ra_fused", "diag"]
+            return ["ra_fused", "ra_fused_mon"]
         if tune and tune.get("naive"):
             return ["prims", "ra_naive", "update", "diag"]
         return ["prims", "ra_zsweep", "update", "diag"]
@@ -102,26 +103,28 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=1,
-                time_families=True, tune=None):
-    """Time `steps` RK steps (+ diagnostics) of one configuration."""
+def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_families=True,
+                tune=None):
+    """Time `steps` RK steps of one configuration, the kinetic energy and
+    enstrophy reduced on the device every step (nsf_rk_step_monitored), with
+    no host synchronisation inside the timed region."""
     shape = (n, n, n)
     phys = W.TGV_PHYS
     dt = W.tgv_dt(n)
     s = nsf.Solver(shape, phys, variant, precision, tune=tune)
     s.init(W.tgv_unperturbed())
+    mon = torch.zeros(2 * max(steps, 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     # warmup; also find the family with the largest summed kernel time
     fam_ms = {}
     fams = families(variant, tune)
     for w in range(max(warmup, 1)):
-        s.step(dt, 1)
-        s.diagnostics()
+        s.step_monitored(dt, 1, mon)
+    s.diagnostics()  # raises on non-finite values
     if time_families:
         for fam in fams:
             nsf.timer_enable(fam)
-            s.step(dt, 1)
-            s.diagnostics()
+            s.step_monitored(dt, 1, mon)
             torch.cuda.synchronize()
             c, ms = nsf.timer_read()
             fam_ms[fam] = ms
@@ -131,15 +134,13 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=
         nsf.timer_enable(dominant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    diag = None
-    for k in range(steps):
-        s.step(dt, 1)
-        if diag_every and (k + 1) % diag_every == 0:
-            diag = s.diagnostics()
+    s.step_monitored(dt, steps, mon)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kcount, kms = nsf.timer_read() if dominant else (0, 0.0)
     nsf.timer_enable(None)
+    monitor = mon.cpu().numpy().reshape(-1, 2)[:steps]
+    diag = s.diagnostics()  # the final state, outside the timed region
     ms_per_step = (t1 - t0) * 1e3 / steps
     rate = n ** 3 * 3 * steps / (t1 - t0)
     out = {
@@ -147,8 +148,10 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, diag_every=
         "ms_per_step": ms_per_step, "pt_rhs_per_s": rate, "dominant": dominant,
         "dominant_launches": kcount, "dominant_ms_total": kms,
         "family_ms_one_step": fam_ms,
-        "ke": float(diag[0]) if diag is not None else None,
-        "enstrophy": float(diag[1]) if diag is not None else None,
+        "ke": float(diag[0]),
+        "enstrophy": float(diag[1]),
+        "monitor_first": [float(x) for x in monitor[0]],
+        "monitor_last": [float(x) for x in monitor[-1]],
     }
     del s
     torch.cuda.empty_cache()
@@ -387,7 +390,8 @@ def main() -> int:
         "config": {"workload": f"taylor-green {n}^3 {args.precision.upper()}, Re=1600 Ma=0.1 Pr=0.71, "
                                f"dt={W.tgv_dt(n)}, KE+enstrophy every step",
                    "variant": main_variant, "tune": main_tune, "selected_by": args.variant,
-                   "n": n, "dt": W.tgv_dt(n), "diag_every": 1},
+                   "n": n, "dt": W.tgv_dt(n), "diag_every": 1,
+                   "diag": "KE and enstrophy reduced on the GPU every step, no host sync"},
         "autotune": tuned,
         "roofline": roofline_of(main_res, args.precision),
         "main": main_res,

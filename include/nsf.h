@@ -152,6 +152,22 @@ int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precis
                 const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
                 double *q_acc, void *r, void *work, size_t work_bytes, void *stream);
 
+/* nsf_rk_step that also records the kinetic-energy and enstrophy integrals
+ * of Section 3 (after DeBonis 2013) on the device, for monitoring a run
+ * without a host round trip. monitor: device memory, 8-byte aligned,
+ * 2 * nsteps doubles, not overlapping the other buffers; entries 2s and
+ * 2s+1 receive the grid means of rho|u|^2/2 and rho|omega|^2/2 (omega =
+ * curl u by the fourth-order first difference) of the state at the start of
+ * step s, the quantities of out[0] and out[1] of nsf_diagnostics. In the
+ * fused RA form the sums are formed inside the first stage's residual
+ * kernel from the values it already holds; otherwise a diagnostics pass
+ * runs before every step. NSF_EINVAL for a NULL or misaligned monitor.
+ * Asynchronous. */
+int nsf_rk_step_monitored(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
+                          const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
+                          double *q_acc, void *r, void *work, size_t work_bytes,
+                          double *monitor, void *stream);
+
 /* Diagnostics of q (Section 3: kinetic-energy and enstrophy integrals),
  * reduced in double in a fixed order (bitwise reproducible). Waits for the
  * stream, then fills out[NSF_NDIAG] (host memory):

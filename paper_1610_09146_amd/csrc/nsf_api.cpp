@@ -115,8 +115,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t prim = 0, deriv = 0, prod = 0, qb = 0, qc = 0, diag_partial = 0, diag_out = 0,
-           total = 0;
+    size_t prim = 0, deriv = 0, prod = 0, qb = 0, qc = 0, mon = 0, diag_partial = 0,
+           diag_out = 0, total = 0;
     int nderiv = 0;
     bool fused = false;
 };
@@ -177,6 +177,12 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
     L.qc = off;
     off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
+    // per-tile (KE, enstrophy) sums of the monitored first stage
+    L.mon = off;
+    off = align_up(off + (L.fused ? 2 * sizeof(double) *
+                                        (size_t)sweep_tiles(d, zchunk_of(d, tune),
+                                                            tile_y_of(d, tune, (int)es))
+                                  : 0));
     L.diag_partial = off;
     off = align_up(off + diag_partial_count(d) * NSF_NDIAG * sizeof(double));
     L.diag_out = off;
@@ -285,11 +291,15 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
     return check_hip("rhs launch");
 }
 
+// monitor (device, 2 * nsteps doubles, or NULL): mean kinetic energy and
+// enstrophy of the state at the start of every step.
 template <typename T>
 int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tune, double dt,
-            int nsteps, T* q, double* qacc, T* r, char* work, const Layout& L, hipStream_t s) {
+            int nsteps, T* q, double* qacc, T* r, char* work, const Layout& L, hipStream_t s,
+            double* monitor = nullptr) {
     static const double A[2] = {2.0 / 3.0, 5.0 / 12.0};
     static const double B[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
+    const double inv_n = 1.0 / (double)d.npts;
     if (L.fused) {
         const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
         const int zc = zchunk_of(d, tune);
@@ -298,17 +308,31 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
         T* qc = (T*)(work + L.qc);
         T* in[3] = {q, qb, qc};
         T* out[3] = {qb, qc, q};
+        double* mpart = (double*)(work + L.mon);
         for (int step = 0; step < nsteps; ++step)
             for (int st = 0; st < 3; ++st) {
                 StageCoef sc;
                 sc.a_dt = st < 2 ? A[st] * dt : 0.0;
                 sc.b_dt = B[st] * dt;
                 sc.last = st == 2;
-                launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s);
+                const bool mon = monitor && st == 0;
+                launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s,
+                                   mon ? mpart : nullptr);
+                if (mon)
+                    launch_monitor_final(mpart, sweep_tiles(d, zc, ty), inv_n, monitor + 2 * step, s);
             }
         return check_hip("rk_step launch");
     }
+    const Coef<double> cd = make_coef<double>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
     for (int step = 0; step < nsteps; ++step) {
+        if (monitor) {
+            // the diagnostics pass writes NDIAG means; KE and enstrophy lead
+            double* dout = (double*)(work + L.diag_out);
+            launch_diag<T>(d, cd, q, (double*)(work + L.diag_partial), dout, s);
+            hipError_t e = hipMemcpyAsync(monitor + 2 * step, dout, 2 * sizeof(double),
+                                          hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return fail(NSF_EHIP, "monitor copy: %s", hipGetErrorString(e));
+        }
         for (int st = 0; st < 3; ++st) {
             int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s);
             if (rc) return rc;
@@ -409,9 +433,10 @@ int nsf_rhs(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
     return rhs_impl<float>(d, phys, variant, tune, (const float*)q, (float*)r, (char*)work, L, s);
 }
 
-int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
-                const nsf_tuning* tune, double dt, int32_t nsteps, void* q, double* q_acc,
-                void* r, void* work, size_t work_bytes, void* stream) {
+namespace {
+int rk_entry(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
+             const nsf_tuning* tune, double dt, int32_t nsteps, void* q, double* q_acc, void* r,
+             void* work, size_t work_bytes, double* monitor, void* stream) {
     Dims d;
     int rc = validate_grid(g, &d);
     if (rc) return rc;
@@ -432,12 +457,34 @@ int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precis
         overlap(q, fb, work, L.total) || overlap(r, fb, work, L.total) ||
         overlap(q_acc, ab, work, L.total))
         return fail(NSF_EINVAL, "q, q_acc, r and work must not overlap");
+    const size_t mb = 2 * sizeof(double) * (size_t)nsteps;
+    if (monitor && (overlap(monitor, mb, q, fb) || overlap(monitor, mb, q_acc, ab) ||
+                    overlap(monitor, mb, r, fb) || overlap(monitor, mb, work, L.total)))
+        return fail(NSF_EINVAL, "monitor must not overlap q, q_acc, r or work");
     hipStream_t s = (hipStream_t)stream;
     if (precision == NSF_F64)
         return rk_impl<double>(d, phys, variant, tune, dt, nsteps, (double*)q, q_acc, (double*)r,
-                               (char*)work, L, s);
+                               (char*)work, L, s, monitor);
     return rk_impl<float>(d, phys, variant, tune, dt, nsteps, (float*)q, q_acc, (float*)r,
-                          (char*)work, L, s);
+                          (char*)work, L, s, monitor);
+}
+}  // namespace
+
+int nsf_rk_step(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
+                const nsf_tuning* tune, double dt, int32_t nsteps, void* q, double* q_acc,
+                void* r, void* work, size_t work_bytes, void* stream) {
+    return rk_entry(g, phys, variant, precision, tune, dt, nsteps, q, q_acc, r, work, work_bytes,
+                    nullptr, stream);
+}
+
+int nsf_rk_step_monitored(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
+                          const nsf_tuning* tune, double dt, int32_t nsteps, void* q,
+                          double* q_acc, void* r, void* work, size_t work_bytes, double* monitor,
+                          void* stream) {
+    if (!monitor) return fail(NSF_EINVAL, "monitor is NULL");
+    if ((uintptr_t)monitor % sizeof(double)) return fail(NSF_EINVAL, "monitor is not 8-byte aligned");
+    return rk_entry(g, phys, variant, precision, tune, dt, nsteps, q, q_acc, r, work, work_bytes,
+                    monitor, stream);
 }
 
 int nsf_diagnostics(const nsf_grid* g, const nsf_phys* phys, int precision, const void* q,
@@ -475,8 +522,8 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 }
 
 static const char* kTimerNames =
-    "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ss_grad_naive,"
-    "ss_naive,ss_grad,ss_zsweep,diag,copy,ra_batch,batch_step";
+    "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ra_fused_mon,"
+    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,diag,copy,ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

@@ -88,6 +88,9 @@ struct ZArgs {
     double a_dt, b_dt;
     int last;
     int zchunk, tiles_x, tiles_y;
+    // fused form, monitored launch: each tile also reduces the kinetic
+    // energy and enstrophy sums of its input state into mpart[2 * tile]
+    double* mpart;
 };
 
 // One instance of a batch: its grid, constants, the three state buffers of
@@ -131,7 +134,14 @@ void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hip
 // q_acc += B dt R. qout must not alias q.
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s);
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s,
+                     double* mpart = nullptr);
+
+// Fold per-tile (KE, enstrophy) sums in tile order into out2[0..1] as means.
+void launch_monitor_final(const double* mpart, int ntiles, double inv_n, double* out2,
+                          hipStream_t s);
+// Tiles of the z-sweep for this grid and tuning.
+int sweep_tiles(const Dims& d, int zchunk, int tile_y);
 
 // diagnostics (nsf_diag.hip); partial holds diag_partial_count(d) * NDIAG doubles
 size_t diag_partial_count(const Dims& d);

@@ -238,9 +238,17 @@ __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3]
     A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
 }
 
+// Residual assembly; om2 receives |omega|^2 with omega = curl u from G
+// (used by the kinetic-energy / enstrophy monitor).
 template <typename T>
 __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rho, const T m[3],
-                                         T E, const T u[3], const Coef<T>& k, T R[5]) {
+                                         T E, const T u[3], const Coef<T>& k, T R[5], T& om2) {
+    {
+        const T ox = A.G[2][1] - A.G[1][2];
+        const T oy = A.G[0][2] - A.G[2][0];
+        const T oz = A.G[1][0] - A.G[0][1];
+        om2 = ox * ox + oy * oy + oz * oz;
+    }
     const T div = A.G[0][0] + A.G[1][1] + A.G[2][2];
     R[0] = T(-0.5) * (A.S0 + rho * div);
     T V[3];
@@ -271,10 +279,12 @@ constexpr int kRing = 5;
 // every halo point is fetched once per plane, in the same iteration in
 // which the neighbouring tile fetches it as interior). Ends with a
 // barrier, so the caller may reuse the LDS for another tile right away.
-template <typename T, int TX, int TY, bool FUSED, bool SS = false>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
-                                            T* __restrict__ sV, T* __restrict__ sH) {
+                                            T* __restrict__ sV, T* __restrict__ sH,
+                                            double2* __restrict__ sM = nullptr) {
     static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
+    static_assert(!MON || FUSED, "the monitor is part of the fused stage");
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -411,6 +421,14 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             }
         }
 
+    // fused form, monitored stage: per-thread sums of rho|u|^2/2 and
+    // rho|omega|^2/2 over the tile's planes (in plane order). Single
+    // precision keeps them in a thread-private LDS slot: its register budget
+    // (three waves per SIMD) has no room for two more doubles.
+    constexpr bool kLdsMon = MON && sizeof(T) == 4;
+    double mke = 0.0, mens = 0.0;
+    if constexpr (kLdsMon) sM[tid] = make_double2(0.0, 0.0);
+
     for (int z = z0; z < z1; ++z) {
         // (a) LDS: ring slot of plane z+2 (velocity) and the plane-z fields;
         // the slot of plane z+2 last held plane z-3, whose readers finished
@@ -476,7 +494,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // fetched here, before the compute, so its latency is covered; in
         // double precision the registers are not there (the spill costs more
         // than the exposed latency) and it is fetched in the epilogue.
-        constexpr bool kEarlyAcc = FUSED && sizeof(T) == 4;
+        constexpr bool kEarlyAcc = FUSED && !MON && sizeof(T) == 4;
         const size_t oidx = (size_t)z * plane + col;
         double acc[FUSED ? 5 : 1];
         if constexpr (kEarlyAcc) {
@@ -592,9 +610,29 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], a1z, a2z);
         }
         T R[5];
+        T om2;
         {
             const T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
-            finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R);
+            finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R, om2);
+        }
+        if constexpr (MON) {
+            if (active) {
+                // kinetic energy and enstrophy of the input state (Section 3
+                // diagnostics), vorticity from the same fourth-order G
+                const double rho = (double)Qz[2].rho;
+                const double u0 = uc[0], u1 = uc[1], u2 = uc[2];
+                const double ke = 0.5 * rho * (u0 * u0 + u1 * u1 + u2 * u2);
+                const double en = 0.5 * rho * (double)om2;
+                if constexpr (kLdsMon) {
+                    double2 m = sM[tid];
+                    m.x += ke;
+                    m.y += en;
+                    sM[tid] = m;
+                } else {
+                    mke += ke;
+                    mens += en;
+                }
+            }
         }
         if (active) {
             if constexpr (FUSED) {
@@ -629,6 +667,68 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Xw[4] = gnx[1];
         }
     }
+    if constexpr (MON) {
+        if constexpr (kLdsMon) {
+            mke = sM[tid].x;
+            mens = sM[tid].y;
+        }
+        {
+            // fixed-order tile reduction: wave shuffles, then waves in order
+            // (the velocity ring, 16-byte aligned, is free after the last
+            // barrier of the loop)
+            double* red = reinterpret_cast<double*>(sV);
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                mke += __shfl_down(mke, off, 64);
+                mens += __shfl_down(mens, off, 64);
+            }
+            if ((tid & 63) == 0) {
+                red[2 * (tid >> 6)] = mke;
+                red[2 * (tid >> 6) + 1] = mens;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double a = 0.0, b = 0.0;
+                for (int w = 0; w < NT / 64; ++w) {
+                    a += red[2 * w];
+                    b += red[2 * w + 1];
+                }
+                A.mpart[2 * t] = a;
+                A.mpart[2 * t + 1] = b;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// One block folds the per-tile monitor sums in tile order.
+__global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict__ mpart, int ntiles,
+                                                      double inv_n, double* __restrict__ out2) {
+    __shared__ double red[8];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < ntiles; i += 256) {
+        a += mpart[2 * i];
+        b += mpart[2 * i + 1];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * (threadIdx.x >> 6)] = a;
+        red[2 * (threadIdx.x >> 6) + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double x = 0.0, y = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            x += red[2 * w];
+            y += red[2 * w + 1];
+        }
+        out2[0] = x * inv_n;
+        out2[1] = y * inv_n;
+    }
 }
 
 // Waves per SIMD the register budget is tuned for: double-precision tiles
@@ -638,15 +738,16 @@ struct Occ {
     static constexpr int kWaves = sizeof(T) == 8 ? 2 : 3;
 };
 
-template <typename T, int TX, int TY, bool FUSED, bool SS>
+template <typename T, int TX, int TY, bool FUSED, bool SS, bool MON>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[7 * G::NPL];
-    __shared__ T sV[kRing * 3 * G::NPL];
+    __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
     __shared__ T sH[FUSED ? 15 * G::NHALO : 1];
-    zsweep_tile<T, TX, TY, FUSED, SS>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH);
+    __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
+    zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sM);
 }
 
 // Persistent batched stage kernel: every workgroup walks the work list of
@@ -684,13 +785,14 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.b_dt = B_[stage] * bd.dt;
         A.last = stage == 2;
         A.zchunk = bd.zchunk;
+        A.mpart = nullptr;
         A.tiles_x = bd.tiles_x;
         A.tiles_y = bd.tiles_y;
         zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV, sH);
     }
 }
 
-template <typename T, int TX, int TY, bool FUSED, bool SS = false>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
 void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     ZArgs<T> a = a0;
     const Dims& d = a.d;
@@ -699,7 +801,7 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     a.tiles_y = (d.ny + TY - 1) / TY;
     const int tiles_z = (d.nz + a.zchunk - 1) / a.zchunk;
     const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * tiles_z);
-    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS>), dim3(nb), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS, MON>), dim3(nb), dim3(TX * TY), 0, s, a);
 }
 
 }  // namespace
@@ -771,11 +873,23 @@ int batch_blocks_per_cu(int tile_y) {
     return e == hipSuccess ? nb : 0;
 }
 
+void launch_monitor_final(const double* mpart, int ntiles, double inv_n, double* out2,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_monitor_final, dim3(1), dim3(256), 0, s, mpart, ntiles, inv_n, out2);
+}
+
+int sweep_tiles(const Dims& d, int zchunk, int tile_y) {
+    int tx, ty, tz, zc;
+    tile_counts(d, zchunk, tile_y, &tx, &ty, &tz, &zc);
+    return tx * ty * tz;
+}
+
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s) {
-    TimerScope ts("ra_fused", s);
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s, double* mpart) {
+    TimerScope ts(mpart ? "ra_fused_mon" : "ra_fused", s);
     ZArgs<T> a{};
+    a.mpart = mpart;
     a.d = d;
     a.k = c;
     a.q = q;
@@ -784,8 +898,13 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
-    if (tile_y == 16) launch_tiles<T, kTX, 16, true>(a, zchunk, s);
-    else launch_tiles<T, kTX, 8, true>(a, zchunk, s);
+    if (mpart) {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, true>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, true, false, true>(a, zchunk, s);
+    } else {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, true>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, true>(a, zchunk, s);
+    }
 }
 
 #define NSF_INST(T)                                                                          \
@@ -797,7 +916,7 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
                                       const T*, T*, int, int, hipStream_t);                 \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
-                                     const StageCoef&, int, int, hipStream_t);
+                                     const StageCoef&, int, int, hipStream_t, double*);
 NSF_INST(float)
 NSF_INST(double)
 #undef NSF_INST

@@ -89,6 +89,8 @@ def lib() -> ctypes.CDLL:
         L.nsf_init_fields.argtypes = [G, P, Tg, ctypes.c_int, vp, vp, vp]
         L.nsf_rhs.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, vp, vp, vp, sz, vp]
         L.nsf_rk_step.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, d, i32, vp, vp, vp, vp, sz, vp]
+        L.nsf_rk_step_monitored.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, d, i32, vp, vp,
+                                            vp, vp, sz, vp, vp]
         L.nsf_diagnostics.argtypes = [G, P, ctypes.c_int, vp, vp, sz, ctypes.POINTER(d), vp]
         L.nsf_device_copy.argtypes = [vp, vp, sz, vp]
         L.nsf_timer_enable.argtypes = [ctypes.c_char_p]
@@ -210,6 +212,19 @@ def rk_step(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, work,
                              work.numel() * work.element_size(), _stream(stream)), "nsf_rk_step")
 
 
+def rk_step_monitored(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, work,
+                      monitor: torch.Tensor, tune: dict | None = None, stream=None) -> None:
+    """rk_step that writes (KE, enstrophy) of the state at the start of every
+    step into ``monitor``, a float64 device tensor of at least 2 * nsteps."""
+    if monitor.dtype != torch.float64 or not monitor.is_contiguous() or monitor.numel() < 2 * nsteps:
+        raise ValueError("monitor must be a contiguous float64 tensor of >= 2 * nsteps elements")
+    _check(lib().nsf_rk_step_monitored(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                                       _variant(variant), _precision(precision), _tuning(tune),
+                                       float(dt), int(nsteps), _ptr(q), _ptr(q_acc), _ptr(r),
+                                       _ptr(work), work.numel() * work.element_size(),
+                                       _ptr(monitor), _stream(stream)), "nsf_rk_step_monitored")
+
+
 def diagnostics(shape, phys, precision, q, work, stream=None, check: bool = True) -> np.ndarray:
     out = (ctypes.c_double * NDIAG)()
     rc = lib().nsf_diagnostics(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
@@ -312,6 +327,10 @@ class Solver:
     def step(self, dt: float, nsteps: int = 1) -> None:
         rk_step(self.shape, self.phys, self.variant, self.precision, dt, nsteps, self.q,
                 self.q_acc, self.r, self.work, self.tune)
+
+    def step_monitored(self, dt: float, nsteps: int, monitor: torch.Tensor) -> None:
+        rk_step_monitored(self.shape, self.phys, self.variant, self.precision, dt, nsteps, self.q,
+                          self.q_acc, self.r, self.work, monitor, self.tune)
 
     def diagnostics(self, check: bool = True) -> np.ndarray:
         return diagnostics(self.shape, self.phys, self.precision, self.q, self.work, check=check)

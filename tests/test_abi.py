@@ -115,6 +115,29 @@ def test_rk_step_validation_before_launch(nsf):
     assert L.nsf_rk_step(*args(0.01, 1, need // 2)) == nsf.EWORKSPACE
 
 
+def test_rk_step_monitored_validation_before_launch(nsf):
+    # fake, never-dereferenced addresses: the monitor checks fail first
+    phys = {"Re": 1600.0, "Ma": 0.1, "Pr": 0.71, "gamma": 1.4}
+    shape = (8, 8, 8)
+    need = nsf.workspace_bytes(shape, "RA", "f64", {"fuse": 1})
+    L = nsf.lib()
+    tune = nsf._tuning({"fuse": 1})
+
+    def call(monitor, nsteps=4):
+        return L.nsf_rk_step_monitored(
+            ctypes.byref(nsf._grid(shape)), ctypes.byref(nsf._phys(phys)), 1, 0, tune, 0.01,
+            nsteps, ctypes.c_void_p(0x1000000), ctypes.c_void_p(0x2000000),
+            ctypes.c_void_p(0x3000000), ctypes.c_void_p(0x4000000), need, monitor, None)
+
+    assert call(None) == nsf.EINVAL
+    assert call(ctypes.c_void_p(0x5000004)) == nsf.EINVAL
+    assert "aligned" in L.nsf_last_error().decode()
+    # monitor inside q
+    assert call(ctypes.c_void_p(0x1000008)) == nsf.EINVAL
+    assert "overlap" in L.nsf_last_error().decode()
+    assert call(ctypes.c_void_p(0x5000000), nsteps=-1) == nsf.EINVAL
+
+
 def test_timer_names(nsf):
     names = nsf.timer_names()
     assert "update" in names and "diag" in names
