@@ -104,7 +104,7 @@ def log(msg: str) -> None:
 
 
 def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_families=True,
-                tune=None):
+                tune=None, tgv=None):
     """Time `steps` RK steps of one configuration, the kinetic energy and
     enstrophy reduced on the device every step (nsf_rk_step_monitored), with
     no host synchronisation inside the timed region."""
@@ -112,7 +112,7 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_famili
     phys = W.TGV_PHYS
     dt = W.tgv_dt(n)
     s = nsf.Solver(shape, phys, variant, precision, tune=tune)
-    s.init(W.tgv_unperturbed())
+    s.init(tgv or W.tgv_unperturbed())
     mon = torch.zeros(2 * max(steps, 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     # warmup; also find the family with the largest summed kernel time
@@ -265,6 +265,33 @@ def batch_precision_errors(nsf, torch, W, steps):
             "ke_rel_err_median": float(np.median(rel))}
 
 
+# Bandwidth of the library's streaming copy on 4 GiB, measured at start-up
+# (the achievable HBM rate next to the vendor peak).
+COPY_PEAK = {}
+
+
+def copy_peak(nsf, torch, gib=4, reps=5):
+    """Read + write bytes / time of nsf_device_copy over `gib` GiB, best of
+    `reps` launches, HIP events on the launch stream."""
+    n = gib << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    nsf.device_copy(src, dst)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nsf.device_copy(src, dst)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": round(2 * n * 8 / best / 1e6, 1), "ms": round(best, 4),
+            "kernel": f"k_copy16 (nsf_device_copy), {gib} GiB read + {gib} GiB written, best of {reps}"}
+
+
 def roofline_of(res, precision):
     fam = res["dominant"]
     if not fam or res["dominant_launches"] == 0:
@@ -279,7 +306,9 @@ def roofline_of(res, precision):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(tag), "traffic_key": tag,
             "algorithmic_bytes_per_launch": alg_bytes,
-            "avg_launch_ms": round(avg_s * 1e3, 4)}
+            "avg_launch_ms": round(avg_s * 1e3, 4),
+            "copy_peak_GBps": COPY_PEAK.get("GBps"),
+            "frac_of_copy": round(achieved / COPY_PEAK["GBps"], 4) if COPY_PEAK else None}
 
 
 def cpu_baseline(W, budget_s=12.0, n=512, planes_per_call=8):
@@ -332,6 +361,8 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     nsf.lib()  # fail loudly if the HIP library is missing
+    COPY_PEAK.update(copy_peak(nsf, torch))
+    log(f"copy peak: {COPY_PEAK['GBps']} GB/s")
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -368,6 +399,14 @@ def main() -> int:
             r = run_variant(nsf, torch, W, n, v, prec, k, 1, tune=tune)
             r["roofline"] = roofline_of(r, prec)
             extras[name] = r
+        # 256^3, every variant, pointwise +-1e-3 perturbation (seed 1610), 100 steps
+        for name, v, tune in (("BL", "BL", None), ("SS", "SS", None),
+                              ("RA_stored_prims", "RA", None), ("RA_fused", "RA", {"fuse": 1})):
+            log(f"extra: 256^3 {name}")
+            r = run_variant(nsf, torch, W, 256, v, "f64", 100, 1, tune=tune,
+                            tgv=W.tgv_pointwise(1610, 1e-3))
+            r["roofline"] = roofline_of(r, "f64")
+            extras[f"n256_{name}_f64"] = r
         for prec in ("f64", "f32"):
             log(f"extra: batch64 {prec}")
             extras[f"batch64_{prec}"] = run_batch(nsf, torch, W, prec, 10)
@@ -393,6 +432,7 @@ def main() -> int:
                    "n": n, "dt": W.tgv_dt(n), "diag_every": 1,
                    "diag": "KE and enstrophy reduced on the GPU every step, no host sync"},
         "autotune": tuned,
+        "copy_peak": COPY_PEAK,
         "roofline": roofline_of(main_res, args.precision),
         "main": main_res,
         "extras": extras,

@@ -255,8 +255,11 @@ int nsf_batch_info(const nsf_batch *b, int32_t *nitems, int32_t *nblocks);
 
 int nsf_batch_destroy(nsf_batch *b);
 
-/* Device-to-device copy of `bytes` with a plain streaming kernel; used to
- * calibrate achievable HBM bandwidth and the memory counters. */
+/* Device-to-device copy of `bytes` with a plain streaming kernel (one
+ * 16-byte element per lane, non-temporal), the reference for achievable HBM
+ * bandwidth and for the memory-counter calibration. src and dst: device
+ * memory, 16-byte aligned (NSF_EINVAL otherwise), not overlapping.
+ * Asynchronous. */
 int nsf_device_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 /* Kernel timer for roofline reporting. nsf_timer_enable(name) records a

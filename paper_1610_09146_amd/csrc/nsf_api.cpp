@@ -517,6 +517,8 @@ int nsf_diagnostics(const nsf_grid* g, const nsf_phys* phys, int precision, cons
 int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
     if (!src || !dst) return fail(NSF_EINVAL, "src and dst must be non-NULL");
     if (overlap(src, bytes, dst, bytes)) return fail(NSF_EINVAL, "src and dst overlap");
+    if ((uintptr_t)src % 16 || (uintptr_t)dst % 16)
+        return fail(NSF_EINVAL, "src and dst must be 16-byte aligned");
     launch_copy(src, dst, bytes, (hipStream_t)stream);
     return check_hip("copy launch");
 }

@@ -23,6 +23,25 @@ namespace nsf {
 
 namespace {
 
+// Streaming accesses of the fused stage: the accumulator and the stage
+// output are touched once per launch and go with the non-temporal hint, so
+// they do not displace the q planes that neighbouring tiles re-read as halo
+// from the L2. (The unfused residual store stays a plain store: the update
+// kernel reads it right after.)
+#ifndef NSF_STREAM_NT
+#define NSF_STREAM_NT 1
+#endif
+template <typename V>
+__device__ __forceinline__ V stream_load(const V* p) {
+    if constexpr (NSF_STREAM_NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename V>
+__device__ __forceinline__ void stream_store(V v, V* p) {
+    if constexpr (NSF_STREAM_NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
 constexpr int kTX = 32;  // tile width; the tile height is 8 or 16 rows
 
@@ -499,7 +518,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         double acc[FUSED ? 5 : 1];
         if constexpr (kEarlyAcc) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) acc[f] = active ? A.qacc[f * n + oidx] : 0.0;
+            for (int f = 0; f < 5; ++f) acc[f] = active ? stream_load(A.qacc + f * n + oidx) : 0.0;
         }
         __syncthreads();
 
@@ -638,14 +657,14 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             if constexpr (FUSED) {
                 if constexpr (!kEarlyAcc) {
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) acc[f] = A.qacc[f * n + oidx];
+                    for (int f = 0; f < 5; ++f) acc[f] = stream_load(A.qacc + f * n + oidx);
                 }
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     const double rr = (double)R[f];
                     const double na = fma(A.b_dt, rr, acc[f]);
-                    A.qacc[f * n + oidx] = na;
-                    A.qout[f * n + oidx] = A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]);
+                    stream_store(na, A.qacc + f * n + oidx);
+                    stream_store(A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]), A.qout + f * n + oidx);
                 }
             } else {
 #pragma unroll
