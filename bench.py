@@ -407,6 +407,14 @@ def main() -> int:
                             tgv=W.tgv_pointwise(1610, 1e-3))
             r["roofline"] = roofline_of(r, "f64")
             extras[f"n256_{name}_f64"] = r
+        # the largest single-GPU grid, 1024^3 (about 215 GB), when it fits
+        torch.cuda.empty_cache()
+        need = nsf.workspace_bytes((1024,) * 3, "RA", "f64", {"fuse": 1}) + 15 * 1024 ** 3 * 8
+        if torch.cuda.mem_get_info()[0] > need + (2 << 30):
+            log("extra: 1024^3 RA fused f64")
+            r = run_variant(nsf, torch, W, 1024, "RA", "f64", 3, 1, tune={"fuse": 1})
+            r["roofline"] = roofline_of(r, "f64")
+            extras["n1024_RA_fused_f64"] = r
         for prec in ("f64", "f32"):
             log(f"extra: batch64 {prec}")
             extras[f"batch64_{prec}"] = run_batch(nsf, torch, W, prec, 10)

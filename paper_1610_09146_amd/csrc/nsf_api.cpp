@@ -172,9 +172,10 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     off = align_up(off + (size_t)L.nderiv * d.npts * es);
     L.prod = off;
     off = align_up(off + (variant == NSF_BL ? d.npts * es : 0));
-    // fused RA stages rotate the state through q -> qb -> qc -> q
-    L.qb = off;
-    off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
+    // fused RA stages rotate the state through q -> qb -> qc -> q. qb shares
+    // the primitive region: nsf_rhs uses the primitives and nsf_rk_step the
+    // rotating state, never both in one call.
+    L.qb = L.fused ? L.prim : off;
     L.qc = off;
     off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
     // per-tile (KE, enstrophy) sums of the monitored first stage

@@ -291,6 +291,19 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
 
 constexpr int kRing = 5;
 
+// Whether the fused form keeps the per-thread halo ring of raw q in LDS
+// (each halo point fetched once per plane) or fetches every halo point twice
+// per plane from the L2 (at the leading plane for its velocity, at the
+// centre plane for its plane fields). Double-precision 32 x 8 tiles drop the
+// ring: without its LDS two workgroups fit on a CU.
+#ifndef NSF_F64_Y8_HALO_RING
+#define NSF_F64_Y8_HALO_RING 0
+#endif
+template <typename T, int TY, bool FUSED>
+constexpr bool halo_ring() {
+    return FUSED && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
+}
+
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
 // holds 7 * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
 // 3 * 5 * NHALO values: the raw conservative values each thread loaded at
@@ -304,6 +317,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                                             double2* __restrict__ sM = nullptr) {
     static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
     static_assert(!MON || FUSED, "the monitor is part of the fused stage");
+    constexpr bool HR = halo_ring<T, TY, FUSED>();
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -408,9 +422,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     u = rp.a[1] * ir;
                     v = rp.a[2] * ir;
                     w = rp.a[3] * ir;
-                    if (s >= 2)
+                    if constexpr (HR)
+                        if (s >= 2)
 #pragma unroll
-                        for (int f = 0; f < 5; ++f) hring(zz, f, h) = rp.a[f];
+                            for (int f = 0; f < 5; ++f) hring(zz, f, h) = rp.a[f];
                 } else {
                     RawV<T, FUSED> rv;
                     load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
@@ -429,11 +444,13 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // seven plane fields of plane z0
     RawP<T, FUSED> hq[HPT];
     RawV<T, FUSED> hv[FUSED ? 1 : HPT];
+    RawP<T, FUSED> hz[FUSED && !HR ? HPT : 1];  // fused, no ring: raw q of plane z
 #pragma unroll
     for (int h = 0; h < HPT; ++h)
         if (hval[h]) {
             if constexpr (FUSED) {
                 load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+                if constexpr (!HR) load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z0) + hcol[h]);
             } else {
                 load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
                 load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0) + hcol[h]);
@@ -475,12 +492,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     v = hq[h].a[2] * ir;
                     w = hq[h].a[3] * ir;
                     // plane-z fields from the raw values parked two planes ago
+                    // (or fetched in the previous iteration)
                     RawP<T, FUSED> rz;
+                    if constexpr (HR) {
 #pragma unroll
-                    for (int f = 0; f < 5; ++f) rz.a[f] = hring(z, f, h);
+                        for (int f = 0; f < 5; ++f) rz.a[f] = hring(z, f, h);
+#pragma unroll
+                        for (int f = 0; f < 5; ++f) hring(z + 2, f, h) = hq[h].a[f];
+                    } else {
+                        rz = hz[h];
+                    }
                     finish_p<T, FUSED>(rz, k, f7);
-#pragma unroll
-                    for (int f = 0; f < 5; ++f) hring(z + 2, f, h) = hq[h].a[f];
                 } else {
                     finish_v<T, FUSED>(hv[h], u, v, w);
                     finish_p<T, FUSED>(hq[h], k, f7);
@@ -504,6 +526,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             if (hval[h]) {
                 if constexpr (FUSED) {
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                    if constexpr (!HR)
+                        load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
                 } else {
                     load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
@@ -764,7 +788,7 @@ k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[7 * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[FUSED ? 15 * G::NHALO : 1];
+    __shared__ T sH[halo_ring<T, TY, FUSED>() ? 15 * G::NHALO : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
     zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sM);
 }
@@ -781,7 +805,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
     using G = Geom<TX, TY>;
     __shared__ T sP[7 * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[15 * G::NHALO];
+    __shared__ T sH[halo_ring<T, TY, true>() ? 15 * G::NHALO : 1];
     const int nb = gridDim.x;
     const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};

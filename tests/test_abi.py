@@ -63,6 +63,9 @@ def test_workspace_sizes(nsf):
     assert sizes["BL"] - sizes["RA"] >= 61 * npts * 8
     s32 = nsf.workspace_bytes((n, n, n), "RA", "f32")
     assert s32 >= 5 * npts * 4 and s32 < sizes["RA"]
+    # the fused form adds one rotating state (the other shares the primitives)
+    fused = nsf.workspace_bytes((n, n, n), "RA", "f64", {"fuse": 1})
+    assert 5 * npts * 8 <= fused - sizes["RA"] < 6 * npts * 8
 
 
 @pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024)])
