@@ -13,10 +13,13 @@ Closed forms used (h = 2 pi / N, k the integer wavenumber):
 so D sin(kx) = k' cos(kx) and D2 sin(kx) = -k''2 sin(kx) exactly on the
 periodic grid (Section 2: fourth-order central differences).
 """
+import os
+
 import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_1610_09146_amd import workloads as W
 
 PHYS = dict(Re=1600.0, Ma=0.1, Pr=0.71, gamma=1.4)  # Section 3
 
@@ -44,12 +47,27 @@ def state_from_prims(rho, u, v, w, p, gamma=1.4):
 
 
 # ---------------------------------------------------------------- generator
+def _golden(name):
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    with open(path) as f:
+        return [line.split() for line in f if line.strip() and not line.startswith("#")]
+
+
 def test_splitmix64_published_vectors():
-    # First outputs of SplitMix64 from state 0 (Steele, Lea & Flood 2014;
-    # the reference values used by the xoshiro/xorshift test suites).
-    assert O.splitmix64(0, 0) == 0xE220A8397B1DCDAF
-    assert O.splitmix64(0, 1) == 0x6E789E6AA1B965F4
-    assert O.splitmix64(0, 2) == 0x06C45D188009454F
+    # first outputs of SplitMix64 from state 0 (tests/golden/splitmix64_vectors.txt)
+    rows = _golden("splitmix64_vectors.txt")
+    assert len(rows) == 3
+    for idx, hexval in rows:
+        assert O.splitmix64(0, int(idx)) == int(hexval, 16)
+
+
+def test_taylor_green_setup_matches_paper():
+    # the workload recipes carry the paper's Section 3 parameters
+    g = {k: float(v) for k, v in _golden("tgv_setup.txt")}
+    for key in ("Re", "Ma", "Pr", "gamma"):
+        assert W.TGV_PHYS[key] == g[key], key
+    assert W.tgv_dt(64) == g["dt_64"]
+    assert W.tgv_dt(128) == g["dt_64"] / 2 and W.tgv_dt(512) == g["dt_64"] / 8
 
 
 # ---------------------------------------------------------------- operators
