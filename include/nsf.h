@@ -76,8 +76,11 @@ typedef enum { NSF_F64 = 0, NSF_F32 = 1 } nsf_precision;
 #define NSF_NDIAG 16
 
 /* Grid: points per axis on the periodic cube [0, 2*pi)^3 (Section 3).
- * Each n must be >= 5 (distinct radius-2 wrap neighbours) and
- * nx*ny*nz <= 2^31. */
+ * nx and ny must be >= 5 (distinct radius-2 wrap neighbours); nz >= 5, or
+ * nz = 1 for a two-dimensional problem (the z-independent flow: every
+ * z-difference vanishes, and w stays 0 when it starts at 0; the Taylor-Green
+ * initial state is then its z = 0 plane). nx*ny*nz <= 2^31. The batched form
+ * takes cubes only. */
 typedef struct { int32_t nx, ny, nz; } nsf_grid;
 
 /* Non-dimensional parameters of eqs (4)-(7): Reynolds, Mach, Prandtl

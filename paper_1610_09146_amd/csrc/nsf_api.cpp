@@ -194,8 +194,11 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
 
 int validate_grid(const nsf_grid* g, Dims* d) {
     if (!g) return fail(NSF_EINVAL, "grid is NULL");
-    if (g->nx < 5 || g->ny < 5 || g->nz < 5)
-        return fail(NSF_EINVAL, "grid %dx%dx%d: every axis needs >= 5 points", g->nx, g->ny, g->nz);
+    // radius-2 stencils need five distinct points per axis; nz = 1 is the
+    // two-dimensional (z-independent) problem, where every z-difference is 0
+    if (g->nx < 5 || g->ny < 5 || (g->nz < 5 && g->nz != 1))
+        return fail(NSF_EINVAL, "grid %dx%dx%d: x and y need >= 5 points, z >= 5 or 1 (2D)",
+                    g->nx, g->ny, g->nz);
     const size_t n = (size_t)g->nx * g->ny * g->nz;
     if (n > (size_t)1 << 31) return fail(NSF_EINVAL, "grid has %zu points, limit 2^31", n);
     d->nx = g->nx;

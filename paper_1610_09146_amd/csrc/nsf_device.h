@@ -37,7 +37,12 @@ struct Coef {
     T kappa;       // 1/((gamma-1) Ma^2 Pr Re), eq (5)
 };
 
-__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+// periodic index for offsets |i - [0, n)| <= 2: one period when n >= 3, a
+// full modulo for the single-plane (two-dimensional) axis
+__device__ __forceinline__ int wrap(int i, int n) {
+    i = i < 0 ? i + n : (i >= n ? i - n : i);
+    return (i < 0 || i >= n) ? ((i % n) + n) % n : i;
+}
 
 template <typename T>
 __device__ __forceinline__ T d1(T fm2, T fm1, T fp1, T fp2, T a1, T a2) {

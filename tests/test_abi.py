@@ -68,7 +68,8 @@ def test_workspace_sizes(nsf):
     assert 5 * npts * 8 <= fused - sizes["RA"] < 6 * npts * 8
 
 
-@pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024)])
+@pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024),
+                                   (8, 8, 2), (8, 8, 4), (1, 8, 8), (8, 1, 8)])
 def test_bad_grid_rejected(nsf, shape):
     with pytest.raises(nsf.NsfError) as ei:
         nsf.workspace_bytes(shape, "RA", "f64")
@@ -144,3 +145,10 @@ def test_rk_step_monitored_validation_before_launch(nsf):
 def test_timer_names(nsf):
     names = nsf.timer_names()
     assert "update" in names and "diag" in names
+
+
+def test_two_dimensional_grid_accepted(nsf):
+    # nz = 1 is the z-independent (two-dimensional) problem
+    n = nsf.workspace_bytes((16, 12, 1), "RA", "f64")
+    assert n >= 5 * 16 * 12 * 8
+

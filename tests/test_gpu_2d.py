@@ -1,0 +1,129 @@
+"""GPU: two-dimensional grids (nz = 1, the z-independent problem).
+
+Every kernel takes a single z-plane: all z-differences vanish, so the GPU
+residual of a state with w = 0 has R(rho w) exactly zero (the stencils
+difference equal values). Parity against the oracle uses a state with a
+nonzero w so that every field is exercised; bars as in the three-dimensional
+tests: max(1e-12, 4F) per residual (F the oracle's own double-precision
+error on the same input), 1e-10 after ten RK steps, and for the FP32 form 4x
+the effect of rounding the input to float.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1610_09146_amd import workloads as W
+from tests.helpers import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1610_09146_amd import nsf  # noqa: E402
+
+PHYS = W.TGV_PHYS
+SHAPES = [(48, 40, 1), (37, 21, 1), (70, 11, 1)]
+CASES = [("BL", None), ("RA", None), ("SS", None), ("RA", {"naive": 1}), ("SS", {"naive": 1}),
+         ("RA", {"block_y": 8}), ("RA", {"block_y": 16})]
+
+
+def state2d(shape, seed=3):
+    """Perturbed Taylor-Green plane plus a z-velocity w = 0.05 sin x cos 2y."""
+    nx, ny, _ = shape
+    q = O.init(shape, PHYS, W.tgv_pointwise(seed, 1e-2), prec="ld")
+    x = 2 * np.pi * np.arange(nx) / nx
+    y = 2 * np.pi * np.arange(ny) / ny
+    w = 0.05 * np.sin(x)[None, :] * np.cos(2 * y)[:, None]
+    q[3, 0] = q[0, 0] * w
+    q[4, 0] += 0.5 * q[0, 0] * w * w
+    return q
+
+
+def gpu_rhs(shape, variant, precision, q_np, tune=None):
+    s = nsf.Solver(shape, PHYS, variant, precision, tune=tune)
+    s.q.copy_(torch.from_numpy(np.ascontiguousarray(q_np)).to(s.q.dtype))
+    s.rhs()
+    torch.cuda.synchronize()
+    return s.r.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("variant,tune", CASES)
+def test_2d_rhs_f64(shape, variant, tune):
+    print(f"case 2d rhs {variant} {tune} {shape}", flush=True)
+    q = state2d(shape)
+    ref = O.rhs(q, PHYS, prec="ld")
+    floor = rel_err(O.rhs(q.astype(np.float64), PHYS, prec="d"), ref)
+    got = gpu_rhs(shape, variant, "f64", q.astype(np.float64), tune)
+    err = rel_err(got, ref)
+    assert np.all(err <= np.maximum(1e-12, 4 * floor)), (err, floor)
+
+
+@pytest.mark.parametrize("variant,tune", CASES)
+def test_2d_no_z_momentum_generated(variant, tune):
+    # w = 0 in two dimensions: R(rho w) is exactly zero on the GPU
+    shape = (48, 40, 1)
+    q = O.init(shape, PHYS, W.tgv_pointwise(5, 1e-2), prec="d")
+    for precision in ("f64", "f32"):
+        got = gpu_rhs(shape, variant, precision, q, tune)
+        assert np.all(got[3] == 0), (variant, precision)
+        assert np.abs(got[1]).max() > 0
+
+
+@pytest.mark.parametrize("variant,tune", [("RA", {"fuse": 1}), ("RA", None), ("SS", None),
+                                          ("BL", None)])
+def test_2d_rk_ten_steps(variant, tune):
+    shape = (48, 40, 1)
+    print(f"case 2d rk10 {variant} {tune}", flush=True)
+    q = state2d(shape)
+    dt = W.tgv_dt(48)
+    ref = O.rk_step(q, PHYS, dt, 10, prec="ld")
+    s = nsf.Solver(shape, PHYS, variant, "f64", tune=tune)
+    qt = torch.from_numpy(q.astype(np.float64))
+    s.q.copy_(qt)
+    s.q_acc.copy_(qt)
+    s.step(dt, 10)
+    err = rel_err(s.q.cpu().numpy(), ref)
+    assert np.all(err <= 1e-10), err
+
+
+@pytest.mark.parametrize("variant", ["BL", "RA", "SS"])
+def test_2d_rhs_f32_form(variant):
+    shape = (48, 40, 1)
+    q = state2d(shape)
+    q32 = q.astype(np.float32)
+    ref = O.rhs(q32.astype(np.longdouble), PHYS, prec="ld")
+    got = gpu_rhs(shape, variant, "f32", q32)
+    bar = 4 * rel_err(O.rhs(q32.astype(np.longdouble), PHYS, prec="ld"),
+                      O.rhs(q, PHYS, prec="ld"))
+    assert np.all(rel_err(got, ref) <= bar), (rel_err(got, ref), bar)
+
+
+def test_2d_monitor_and_rate_closed_forms():
+    # the z = 0 plane of the Taylor-Green state: KE(0) = 1/4 and enstrophy(0)
+    # = k'^2 (1/2 - 3 gamma M^2/32) from the monitored step; the GPU residual
+    # gives the initial decay rate (2 k''^2 + (k''^2 - k'^2)/3) / (2 Re). (The
+    # 3D pressure at z = 0 is not the 2D equilibrium, so the rate moves
+    # quickly and is read off the residual, not a difference of KE.)
+    n = 64
+    h = 2 * np.pi / n
+    kp = (8 * np.sin(h) - np.sin(2 * h)) / (6 * h)
+    kpp2 = (15 - 16 * np.cos(h) + np.cos(2 * h)) / (6 * h * h)
+    s = nsf.Solver((n, n, 1), PHYS, "RA", "f64", tune={"fuse": 1})
+    s.init(W.tgv_unperturbed())
+    r = s.rhs().cpu().numpy()
+    q = s.q.cpu().numpy()
+    u = q[1:4] / q[0]
+    rate = np.mean(np.sum(u * r[1:4], axis=0) - 0.5 * np.sum(u * u, axis=0) * r[0])
+    rate0 = -(2 * kpp2 + (kpp2 - kp ** 2) / 3) / (2 * PHYS["Re"])
+    # the residual's momentum terms reach ~1e3 times the rate and carry ~1e-13
+    # relative rounding: bar 1e-9
+    assert abs(rate - rate0) <= 1e-9 * abs(rate0), (rate, rate0)
+    mon = torch.zeros(2, dtype=torch.float64, device="cuda")
+    s.step_monitored(W.tgv_dt(n), 1, mon)
+    ke, ens = mon.cpu().numpy()
+    assert abs(ke - 0.25) <= 1e-14
+    ens0 = kp ** 2 * (0.5 - 3 * PHYS["gamma"] * PHYS["Ma"] ** 2 / 32)
+    assert abs(ens - ens0) <= 1e-13 * ens0

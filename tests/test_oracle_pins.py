@@ -380,3 +380,64 @@ def test_slab_entry_points_match_full_grid():
         assert np.array_equal(qs, q[:, idx])
         rs = O.rhs_slab(qs, 16, PHYS)
         assert np.array_equal(rs, r[:, idx[2:4]])
+
+
+# ------------------------------------------------------------ two dimensions
+# nz = 1: the z-independent problem (the paper counts its arrays for 2D as
+# well as 3D, Section 2). The Taylor-Green initial state is its z = 0 plane,
+# u = sin x cos y, v = -cos x sin y, w = 0, p = 1/(gamma M^2) + 3(cos 2x + cos 2y)/16.
+
+@pytest.mark.parametrize("N", [8, 16, 32])
+def test_2d_closed_forms(N):
+    h = 2 * np.pi / N
+    q = O.init((N, N, 1), PHYS, {})
+    d = O.diagnostics(q, PHYS)
+    # KE = <rho |u|^2 / 2> = 1/4: the density variation is orthogonal to |u|^2
+    assert abs(d[0] - 0.25) < 1e-14
+    assert abs(d[2] - 1.0) < 1e-14
+    # omega = (0, 0, 2 k' sin x sin y) and rho = 1 + 3 gamma M^2 (cos 2x + cos 2y)/16:
+    # enstrophy = k'^2 (1/2 - 3 gamma M^2 / 32)
+    ens = kp(1, h) ** 2 * (0.5 - 3 * PHYS["gamma"] * PHYS["Ma"] ** 2 / 32)
+    assert abs(d[1] - ens) < 1e-13 * ens
+    r = O.rhs(q, PHYS, prec="ld")
+    # no z-momentum is generated: every z-difference vanishes (to one
+    # rounding of the stencil's weighted sum, which the oracle evaluates term
+    # by term)
+    assert np.abs(r[3]).max() <= 1e-15 * np.abs(r[1]).max()
+    # initial rate: two directions of D2 plus the 1/3 cross form; convection
+    # and pressure cancel on the divergence-free state as in three dimensions
+    prim = O.prims(q, PHYS)
+    u = prim[:3]
+    rr = r.astype(np.float64)
+    rate = np.mean(np.sum(u * rr[1:4], axis=0) - 0.5 * np.sum(u * u, axis=0) * rr[0])
+    expect = -(2 * kpp2(1, h) + (kpp2(1, h) - kp(1, h) ** 2) / 3) / (2 * PHYS["Re"])
+    assert abs(rate - expect) < 1e-12 * abs(expect)
+
+
+@pytest.mark.parametrize("shape", [(16, 12, 1), (11, 9, 1)])
+def test_2d_equals_z_uniform_3d(shape):
+    # the residual of a z-independent state does not depend on nz: nz = 1
+    # against the same plane repeated on nz = 5, with a nonzero w so that the
+    # z-momentum equation is exercised too
+    nx, ny, _ = shape
+    q2 = O.init(shape, PHYS, {"pert_kind": 1, "pert_amp": 1e-2, "seed": 3}).astype(np.longdouble)
+    x = 2 * np.pi * np.arange(nx) / nx
+    y = 2 * np.pi * np.arange(ny) / ny
+    w = 0.05 * np.sin(x)[None, :] * np.cos(2 * y)[:, None]
+    q2[3, 0] = q2[0, 0] * w
+    q2[4, 0] += 0.5 * q2[0, 0] * w * w
+    q3 = np.repeat(q2, 5, axis=1)
+    r2 = O.rhs(q2, PHYS, prec="ld")
+    r3 = O.rhs(q3, PHYS, prec="ld")
+    assert np.any(r2[3] != 0)
+    for k in range(5):
+        # the z second difference of a constant leaves a rounding residue of
+        # the stencil weights (their sum is 0 only in exact arithmetic)
+        assert np.all(rel_err_ld(r3[:, k:k + 1], r2) <= 1e-15), k
+
+
+def rel_err_ld(a, b):
+    a = np.asarray(a).reshape(a.shape[0], -1)
+    b = np.asarray(b).reshape(b.shape[0], -1)
+    return (np.abs(a - b).max(axis=1) / np.maximum(np.abs(b).max(axis=1), 1e-300)).astype(np.float64)
+
