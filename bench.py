@@ -376,7 +376,7 @@ def main() -> int:
     if args.variant == "AUTO":
         for prec in ("f64", "f32"):
             log(f"autotune {n}^3 {prec}")
-            tuned[prec] = nsf.autotune((n, n, n), W.TGV_PHYS, prec, quick=True, steps=2)
+            tuned[prec] = nsf.autotune((n, n, n), W.TGV_PHYS, prec, quick=True, steps=3)
             log(f"  -> {tuned[prec]}")
         main_variant, main_tune = tuned[args.precision]["variant"], tuned[args.precision]["tune"]
     else:

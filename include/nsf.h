@@ -193,7 +193,9 @@ int nsf_diagnostics(const nsf_grid *g, const nsf_phys *phys, int precision,
  * against the untiled reference residual on a seeded perturbed
  * Taylor-Green state of the same grid (relative max-norm difference at most
  * 1e-10 in double, 1e-3 in single precision); only passing candidates are
- * timed (`steps` RK steps each). The winner is recorded for NSF_AUTO and,
+ * timed (`steps` RK steps each). Candidates within 2% of the fastest count
+ * as ties, resolved toward the default tuning and then the larger z-chunk.
+ * The winner is recorded for NSF_AUTO and,
  * if cache_path is not NULL, appended as one JSON line to that file.
  * Synchronous. Allocates its own device buffers (about 4 states and the
  * largest candidate's work) for the duration of the call. */

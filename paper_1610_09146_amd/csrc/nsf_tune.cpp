@@ -266,6 +266,25 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     cleanup();
     if (rc) return rc;
     if (win.variant < 0) return tfail(NSF_EUNSUPPORTED, "autotune: no candidate passed the parity gate");
+    // Candidates within 2% of the fastest are ties (a few timed steps do not
+    // separate them reliably): the library default wins a tie, then the
+    // larger z-chunk, so repeated runs settle on the same choice.
+    {
+        const double tie = 0.98 * win.pt_rhs_per_s;
+        const int es = precision == NSF_F64 ? 8 : 4;
+        auto is_default = [&](const nsf_tune_result& r) {
+            return r.variant == NSF_RA && r.tune.fuse && !r.tune.naive &&
+                   r.tune.block_y == default_tile_y(es, d) && r.tune.zchunk == default_zchunk(d);
+        };
+        const nsf_tune_result* pick = nullptr;
+        for (const auto& c : cands) {
+            if (!(c.pt_rhs_per_s >= tie)) continue;
+            if (!pick || (is_default(c) && !is_default(*pick)) ||
+                (is_default(c) == is_default(*pick) && c.tune.zchunk > pick->tune.zchunk))
+                pick = &c;
+        }
+        if (pick) win = *pick;
+    }
     *best = win;
     remember(g, precision, win);
     if (cache_path && *cache_path) return append_cache(cache_path, g, precision, win);

@@ -304,8 +304,24 @@ constexpr bool halo_ring() {
     return FUSED && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
 }
 
+// Plane fields kept in LDS with their halo: rho, E, p, T (momentum at a
+// neighbour is rebuilt as rho * u from the velocity ring). Two buffers
+// alternate by plane parity, so the writes of plane z+1 never meet the reads
+// of plane z and one barrier per plane suffices: the ring slot a plane
+// recycles (z+3, the slot of z-2) is read at that point only for the own
+// column, by the thread that writes it.
+constexpr int kPF = 4;
+// The stored-gradient form runs at the register limit; rebuilding momentum
+// would spill there, so it keeps seven plane fields in one buffer (momentum
+// stored) and a second barrier per plane.
+template <bool SS>
+struct PlaneLds {
+    static constexpr int kFields = SS ? 7 : kPF;
+    static constexpr int kBuffers = SS ? 1 : 2;
+};
+
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
-// holds 7 * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
+// holds 2 * kPF * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
 // 3 * 5 * NHALO values: the raw conservative values each thread loaded at
 // its halo point for planes z .. z+2 (a per-thread ring kept in LDS, so
 // every halo point is fetched once per plane, in the same iteration in
@@ -473,13 +489,18 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         Vl[own] = unew[0];
         Vl[NPL + own] = unew[1];
         Vl[2 * NPL + own] = unew[2];
-        sP[own] = Qz[2].rho;
-        sP[NPL + own] = Qz[2].m0;
-        sP[2 * NPL + own] = Qz[2].m1;
-        sP[3 * NPL + own] = Qz[2].m2;
-        sP[4 * NPL + own] = Qz[2].E;
-        sP[5 * NPL + own] = Qz[2].p;
-        sP[6 * NPL + own] = Qz[2].t;
+        constexpr int PF = PlaneLds<SS>::kFields;
+        T* Pz = sP + (PlaneLds<SS>::kBuffers == 2 ? (z & 1) * PF * NPL : 0);  // plane z
+        // field slots: rho, E, p, T, then (stored-gradient form) m0, m1, m2
+        Pz[own] = Qz[2].rho;
+        Pz[NPL + own] = Qz[2].E;
+        Pz[2 * NPL + own] = Qz[2].p;
+        Pz[3 * NPL + own] = Qz[2].t;
+        if constexpr (PF == 7) {
+            Pz[4 * NPL + own] = Qz[2].m0;
+            Pz[5 * NPL + own] = Qz[2].m1;
+            Pz[6 * NPL + own] = Qz[2].m2;
+        }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
@@ -510,8 +531,15 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 Vl[hidx[h]] = u;
                 Vl[NPL + hidx[h]] = v;
                 Vl[2 * NPL + hidx[h]] = w;
-#pragma unroll
-                for (int f = 0; f < 7; ++f) sP[f * NPL + hidx[h]] = f7[f];
+                Pz[hidx[h]] = f7[0];
+                Pz[NPL + hidx[h]] = f7[4];
+                Pz[2 * NPL + hidx[h]] = f7[5];
+                Pz[3 * NPL + hidx[h]] = f7[6];
+                if constexpr (PF == 7) {
+                    Pz[4 * NPL + hidx[h]] = f7[1];
+                    Pz[5 * NPL + hidx[h]] = f7[2];
+                    Pz[6 * NPL + hidx[h]] = f7[3];
+                }
             }
         // (b) prefetch the next iteration's loads
         Raw<T, FUSED> nxt;
@@ -561,16 +589,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
                 const int o = own + s - 2;
-                rho[s] = sP[o];
-                m[0][s] = sP[NPL + o];
-                m[1][s] = sP[2 * NPL + o];
-                m[2][s] = sP[3 * NPL + o];
-                E[s] = sP[4 * NPL + o];
-                p[s] = sP[5 * NPL + o];
-                tt[s] = sP[6 * NPL + o];
+                rho[s] = Pz[o];
+                E[s] = Pz[NPL + o];
+                p[s] = Pz[2 * NPL + o];
+                tt[s] = Pz[3 * NPL + o];
                 vel[0][s] = Vc[o];
                 vel[1][s] = Vc[NPL + o];
                 vel[2][s] = Vc[2 * NPL + o];
+                if constexpr (PF == 7) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * NPL + o];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
+                }
             }
             fold_dir<T, 0>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
         }
@@ -579,16 +611,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
                 const int o = own + (s - 2) * LX;
-                rho[s] = sP[o];
-                m[0][s] = sP[NPL + o];
-                m[1][s] = sP[2 * NPL + o];
-                m[2][s] = sP[3 * NPL + o];
-                E[s] = sP[4 * NPL + o];
-                p[s] = sP[5 * NPL + o];
-                tt[s] = sP[6 * NPL + o];
+                rho[s] = Pz[o];
+                E[s] = Pz[NPL + o];
+                p[s] = Pz[2 * NPL + o];
+                tt[s] = Pz[3 * NPL + o];
                 vel[0][s] = Vc[o];
                 vel[1][s] = Vc[NPL + o];
                 vel[2][s] = Vc[2 * NPL + o];
+                if constexpr (PF == 7) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * NPL + o];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
+                }
             }
             fold_dir<T, 1>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
         }
@@ -695,8 +731,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 for (int f = 0; f < 5; ++f) A.r[f * n + oidx] = R[f];
             }
         }
-        __syncthreads();
-        // (e) rotate the queues
+        if constexpr (PlaneLds<SS>::kBuffers == 1) __syncthreads();
+        // (e) rotate the queues (double-buffered plane fields: no barrier, see kPF)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             Qz[s] = Qz[s + 1];
@@ -710,6 +746,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Xw[4] = gnx[1];
         }
     }
+    __syncthreads();  // every read of the tile's LDS is done
     if constexpr (MON) {
         if constexpr (kLdsMon) {
             mke = sM[tid].x;
@@ -786,7 +823,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
-    __shared__ T sP[7 * G::NPL];
+    __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, FUSED>() ? 15 * G::NHALO : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
@@ -803,7 +840,7 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
 k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items, int nitems,
            int stage) {
     using G = Geom<TX, TY>;
-    __shared__ T sP[7 * G::NPL];
+    __shared__ T sP[2 * kPF * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, true>() ? 15 * G::NHALO : 1];
     const int nb = gridDim.x;
