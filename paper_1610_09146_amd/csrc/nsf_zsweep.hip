@@ -299,8 +299,12 @@ constexpr int kRing = 5;
 #ifndef NSF_F64_Y8_HALO_RING
 #define NSF_F64_Y8_HALO_RING 0
 #endif
-template <typename T, int TY, bool FUSED>
+// The single-precision monitored build drops it too: its per-thread
+// monitor slots and the ring together would exceed the LDS at which three
+// workgroups fit on a CU.
+template <typename T, int TY, bool FUSED, bool MON = false>
 constexpr bool halo_ring() {
+    if (MON && sizeof(T) == 4) return false;
     return FUSED && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
 }
 
@@ -333,7 +337,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                                             double2* __restrict__ sM = nullptr) {
     static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
     static_assert(!MON || FUSED, "the monitor is part of the fused stage");
-    constexpr bool HR = halo_ring<T, TY, FUSED>();
+    constexpr bool HR = halo_ring<T, TY, FUSED, MON>();
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -825,7 +829,7 @@ k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, FUSED>() ? 15 * G::NHALO : 1];
+    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 15 * G::NHALO : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
     zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sM);
 }
