@@ -183,6 +183,22 @@ def version() -> int:
     return int(lib().nsf_version())
 
 
+def _fields(shape, precision, **tensors) -> None:
+    """Check that every given state tensor holds 5 fields of the grid in the
+    right dtype (q, r: the precision's dtype; q_acc: float64): the library
+    takes plain pointers and cannot see the allocation sizes."""
+    nx, ny, nz = (int(v) for v in shape)
+    need = 5 * nx * ny * nz
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        dt = torch.float64 if name == "q_acc" else field_dtype(precision)
+        if t.dtype != dt:
+            raise NsfError(EINVAL, f"{name} must be {dt}, got {t.dtype}")
+        if t.numel() != need:
+            raise NsfError(EINVAL, f"{name} must hold 5 x {nx}x{ny}x{nz} values, got {t.numel()}")
+
+
 def workspace_bytes(shape, variant, precision, tune: dict | None = None) -> int:
     out = ctypes.c_size_t(0)
     _check(lib().nsf_workspace_bytes(ctypes.byref(_grid(shape)), _variant(variant),
@@ -193,12 +209,14 @@ def workspace_bytes(shape, variant, precision, tune: dict | None = None) -> int:
 
 def init_fields(shape, phys, tgv, precision, q: torch.Tensor, q_acc: torch.Tensor | None,
                 stream=None) -> None:
+    _fields(shape, precision, q=q, q_acc=q_acc)
     _check(lib().nsf_init_fields(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
                                  ctypes.byref(_tgv(tgv)), _precision(precision), _ptr(q),
                                  _ptr(q_acc), _stream(stream)), "nsf_init_fields")
 
 
 def rhs(shape, phys, variant, precision, q, r, work, tune: dict | None = None, stream=None) -> None:
+    _fields(shape, precision, q=q, r=r)
     _check(lib().nsf_rhs(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)), _variant(variant),
                          _precision(precision), _tuning(tune), _ptr(q), _ptr(r), _ptr(work),
                          work.numel() * work.element_size(), _stream(stream)), "nsf_rhs")
@@ -206,6 +224,7 @@ def rhs(shape, phys, variant, precision, q, r, work, tune: dict | None = None, s
 
 def rk_step(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, work,
             tune: dict | None = None, stream=None) -> None:
+    _fields(shape, precision, q=q, q_acc=q_acc, r=r)
     _check(lib().nsf_rk_step(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
                              _variant(variant), _precision(precision), _tuning(tune), float(dt),
                              int(nsteps), _ptr(q), _ptr(q_acc), _ptr(r), _ptr(work),
@@ -218,6 +237,7 @@ def rk_step_monitored(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, 
     step into ``monitor``, a float64 device tensor of at least 2 * nsteps."""
     if monitor.dtype != torch.float64 or not monitor.is_contiguous() or monitor.numel() < 2 * nsteps:
         raise ValueError("monitor must be a contiguous float64 tensor of >= 2 * nsteps elements")
+    _fields(shape, precision, q=q, q_acc=q_acc, r=r)
     _check(lib().nsf_rk_step_monitored(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
                                        _variant(variant), _precision(precision), _tuning(tune),
                                        float(dt), int(nsteps), _ptr(q), _ptr(q_acc), _ptr(r),
@@ -226,6 +246,7 @@ def rk_step_monitored(shape, phys, variant, precision, dt, nsteps, q, q_acc, r, 
 
 
 def diagnostics(shape, phys, precision, q, work, stream=None, check: bool = True) -> np.ndarray:
+    _fields(shape, precision, q=q)
     out = (ctypes.c_double * NDIAG)()
     rc = lib().nsf_diagnostics(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
                                _precision(precision), _ptr(q), _ptr(work),

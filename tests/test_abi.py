@@ -152,3 +152,18 @@ def test_two_dimensional_grid_accepted(nsf):
     n = nsf.workspace_bytes((16, 12, 1), "RA", "f64")
     assert n >= 5 * 16 * 12 * 8
 
+
+
+def test_binding_checks_state_sizes_and_dtypes(nsf):
+    # the library takes plain pointers; the binding rejects tensors that do
+    # not hold five fields of the grid in the right dtype before any call
+    import torch
+    shape = (8, 8, 8)
+    good = torch.zeros(5 * 8 ** 3, dtype=torch.float64)
+    nsf._fields(shape, "f64", q=good, q_acc=good, r=good)
+    with pytest.raises(nsf.NsfError):
+        nsf._fields(shape, "f64", q=good[:-1])
+    with pytest.raises(nsf.NsfError):
+        nsf._fields(shape, "f32", q=good)
+    with pytest.raises(nsf.NsfError):
+        nsf._fields(shape, "f32", q=good.float(), q_acc=good.float())
