@@ -4,6 +4,10 @@
 // eqs (1)-(10)).
 #pragma once
 
+#ifndef NSF_NEWTON_RCP
+#define NSF_NEWTON_RCP 1
+#endif
+
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -54,8 +58,31 @@ __device__ __forceinline__ T d2(T fm2, T fm1, T f0, T fp1, T fp2, T b0, T b1, T 
     return b0 * f0 + b1 * (fp1 + fm1) + b2 * (fp2 + fm2);
 }
 
+// 1/x for the density (normal, far from 0 and infinity): the hardware
+// reciprocal estimate refined by Newton-Raphson steps e = 1 - x r, r + r e
+// (Markstein). The double estimate carries about 24 bits, so double takes
+// two steps (measured on gfx950: equal to the rounded quotient 1/x on 2^20
+// densities in [0.9, 1.1]); the single estimate is within an ulp and one
+// step gives the rounded quotient on the same sample. About half the
+// instructions of the IEEE division sequence.
 template <typename T>
-__device__ __forceinline__ T fast_rcp(T x) { return T(1) / x; }
+__device__ __forceinline__ T fast_rcp(T x) {
+#if NSF_NEWTON_RCP
+    if constexpr (sizeof(T) == 8) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = fma(-x, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-x, r, 1.0);
+        return fma(r, e, r);
+    } else {
+        const float r = __builtin_amdgcn_rcpf(x);
+        const float e = fmaf(-x, r, 1.0f);
+        return fmaf(r, e, r);
+    }
+#else
+    return T(1) / x;
+#endif
+}
 
 // Primitive variables from one point's conservative values, eqs (8)-(9):
 // u_a = (rho u_a)/rho, p = (gamma-1)(rho E - rho|u|^2/2), T = gamma Ma^2 p/rho.
