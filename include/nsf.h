@@ -79,8 +79,9 @@ typedef enum { NSF_F64 = 0, NSF_F32 = 1 } nsf_precision;
  * nx and ny must be >= 5 (distinct radius-2 wrap neighbours); nz >= 5, or
  * nz = 1 for a two-dimensional problem (the z-independent flow: every
  * z-difference vanishes, and w stays 0 when it starts at 0; the Taylor-Green
- * initial state is then its z = 0 plane). nx*ny*nz <= 2^31. The batched form
- * takes cubes only. */
+ * initial state is then its z = 0 plane). nx*ny*nz <= 2^31 and
+ * nx*ny < 2^28 (one z-plane of doubles is addressed with 32-bit byte
+ * offsets). The batched form takes cubes only. */
 typedef struct { int32_t nx, ny, nz; } nsf_grid;
 
 /* Non-dimensional parameters of eqs (4)-(7): Reynolds, Mach, Prandtl

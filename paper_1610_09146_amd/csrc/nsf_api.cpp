@@ -201,6 +201,9 @@ int validate_grid(const nsf_grid* g, Dims* d) {
                     g->nx, g->ny, g->nz);
     const size_t n = (size_t)g->nx * g->ny * g->nz;
     if (n > (size_t)1 << 31) return fail(NSF_EINVAL, "grid has %zu points, limit 2^31", n);
+    // the fused stage addresses one z-plane of doubles with 32-bit byte offsets
+    if ((size_t)g->nx * g->ny >= (size_t)1 << 28)
+        return fail(NSF_EINVAL, "grid plane %dx%d has 2^28 or more points", g->nx, g->ny);
     d->nx = g->nx;
     d->ny = g->ny;
     d->nz = g->nz;

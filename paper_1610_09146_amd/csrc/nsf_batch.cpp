@@ -52,7 +52,8 @@ int check_grids(int32_t count, const nsf_grid* grids, std::vector<Dims>& dims) {
         const nsf_grid& g = grids[i];
         if (g.nx < 5 || g.ny < 5 || g.nz < 5) return bfail(NSF_EINVAL, "batch: every axis needs >= 5 points");
         const size_t n = (size_t)g.nx * g.ny * g.nz;
-        if (n > (size_t)1 << 31) return bfail(NSF_EINVAL, "batch: instance too large");
+        if (n > (size_t)1 << 31 || (size_t)g.nx * g.ny >= (size_t)1 << 28)
+            return bfail(NSF_EINVAL, "batch: instance too large");
         dims[i] = Dims{g.nx, g.ny, g.nz, n};
     }
     return NSF_OK;

@@ -42,6 +42,30 @@ __device__ __forceinline__ void stream_store(V v, V* p) {
     else *p = v;
 }
 
+// Buffer view of one z-plane of one field. The base is uniform, so the
+// descriptor sits in scalar registers and every lane passes a 32-bit byte
+// offset. An offset at or past the plane's size is out of range: the hardware
+// then returns 0 for a load and drops a store, which lets lanes outside the
+// grid skip their accesses without a branch. (The grid check keeps a plane
+// below 2^28 points, so a plane of doubles stays below kOutside bytes.)
+constexpr uint32_t kOutside = 0x80000000u;
+constexpr int kPolicy = NSF_STREAM_NT ? 2 : 0;  // cache-policy bits: non-temporal
+constexpr int kRsrcWord3 = 0x00020000;        // gfx9 family: 32-bit data format
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_view(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+__device__ __forceinline__ double view_load(__amdgpu_buffer_rsrc_t v, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v, off, 0, kPolicy));
+}
+__device__ __forceinline__ void view_store(double x, __amdgpu_buffer_rsrc_t v, uint32_t off) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), v, off, 0, kPolicy);
+}
+__device__ __forceinline__ void view_store(float x, __amdgpu_buffer_rsrc_t v, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v, off, 0, kPolicy);
+}
+
 constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
 constexpr int kTX = 32;  // tile width; the tile height is 8 or 16 rows
 
@@ -338,6 +362,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
     static_assert(!MON || FUSED, "the monitor is part of the fused stage");
     constexpr bool HR = halo_ring<T, TY, FUSED, MON>();
+    // Lean form of the fused stage: no branch between the prefetch and the
+    // next iteration. Halo prefetches run on every lane and the epilogue uses
+    // buffer accesses that drop the lanes outside the grid. With a branch
+    // there, the compiler's count of outstanding memory operations takes the
+    // path without stores, and the wait for the prefetched plane then also
+    // waits for this plane's stores. (The monitored stage keeps the branch
+    // where its sums would not fit the registers without it: in single
+    // precision and in the 8-row double-precision tile.)
+    constexpr bool kLean = FUSED && !(MON && (sizeof(T) == 4 || TY == 8));
+    // Momenta in the z fold: every recomputed-derivative form takes rho * u
+    // from the queue and the velocity ring, as the x and y folds do, instead
+    // of holding the conserved momenta of five planes in registers (this is
+    // where the lean form finds its registers; all forms share the choice so
+    // that they round alike). The stored-gradient form keeps the momenta in
+    // its plane fields.
+    constexpr bool kMomFromVel = !SS;
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -553,9 +593,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             gnx[0] = A.grad[0 * n + poff(z + 3) + col];
             gnx[1] = A.grad[4 * n + poff(z + 3) + col];
         }
+        // (lean form: a halo slot past the end loads the wrapped address of
+        // the tile's corner and leaves it unused)
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            if (hval[h]) {
+            if (kLean || hval[h]) {
                 if constexpr (FUSED) {
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
                     if constexpr (!HR)
@@ -565,16 +607,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
                 }
             }
-        // fused form: the accumulator of plane z. In single precision it is
-        // fetched here, before the compute, so its latency is covered; in
-        // double precision the registers are not there (the spill costs more
-        // than the exposed latency) and it is fetched in the epilogue.
-        constexpr bool kEarlyAcc = FUSED && !MON && sizeof(T) == 4;
+        // fused form: the accumulator of plane z. The lean single-precision
+        // form fetches it here, before the compute, so its latency is
+        // covered; in double precision the registers are not there (the spill
+        // costs more than the exposed latency) and the monitored stage keeps
+        // its registers for the sums, so both fetch it in the epilogue.
+        constexpr bool kEarlyAcc = kLean && sizeof(T) == 4;
         const size_t oidx = (size_t)z * plane + col;
+        const size_t zo = (size_t)z * plane;
+        const uint32_t pb = (uint32_t)(plane * sizeof(double));
+        const uint32_t off = active ? (uint32_t)col * 8u : kOutside;
         double acc[FUSED ? 5 : 1];
         if constexpr (kEarlyAcc) {
 #pragma unroll
-            for (int f = 0; f < 5; ++f) acc[f] = active ? stream_load(A.qacc + f * n + oidx) : 0.0;
+            for (int f = 0; f < 5; ++f) acc[f] = view_load(plane_view(A.qacc + f * n + zo, pb), off);
         }
         __syncthreads();
 
@@ -638,15 +684,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             for (int s = 0; s < 5; ++s) {
                 const T* Vs = ring(z - 2 + s);
                 rho[s] = Qz[s].rho;
-                m[0][s] = Qz[s].m0;
-                m[1][s] = Qz[s].m1;
-                m[2][s] = Qz[s].m2;
                 E[s] = Qz[s].E;
                 p[s] = Qz[s].p;
                 tt[s] = Qz[s].t;
                 vel[0][s] = Vs[own];
                 vel[1][s] = Vs[NPL + own];
                 vel[2][s] = Vs[2 * NPL + own];
+                if constexpr (kMomFromVel) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
+                } else {
+                    m[0][s] = Qz[s].m0;
+                    m[1][s] = Qz[s].m1;
+                    m[2][s] = Qz[s].m2;
+                }
             }
             fold_dir<T, 2>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
         }
@@ -695,7 +746,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         T R[5];
         T om2;
         {
-            const T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
+            T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
+            if constexpr (kMomFromVel)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) mc[a] = Qz[2].rho * uc[a];
             finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R, om2);
         }
         if constexpr (MON) {
@@ -717,7 +771,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 }
             }
         }
-        if (active) {
+        if constexpr (kLean) {
+            const uint32_t pbT = (uint32_t)(plane * sizeof(T));
+            const uint32_t offT = active ? (uint32_t)(col * sizeof(T)) : kOutside;
+            if constexpr (!kEarlyAcc) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) acc[f] = view_load(plane_view(A.qacc + f * n + zo, pb), off);
+            }
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                const double rr = (double)R[f];
+                const double na = fma(A.b_dt, rr, acc[f]);
+                view_store(na, plane_view(A.qacc + f * n + zo, pb), off);
+                view_store(A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]),
+                           plane_view(A.qout + f * n + zo, pbT), offT);
+            }
+        } else if (active) {
             if constexpr (FUSED) {
                 if constexpr (!kEarlyAcc) {
 #pragma unroll

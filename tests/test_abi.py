@@ -69,11 +69,20 @@ def test_workspace_sizes(nsf):
 
 
 @pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024),
-                                   (8, 8, 2), (8, 8, 4), (1, 8, 8), (8, 1, 8)])
+                                   (8, 8, 2), (8, 8, 4), (1, 8, 8), (8, 1, 8),
+                                   (16384, 16384, 1), (1 << 20, 256, 5)])
 def test_bad_grid_rejected(nsf, shape):
     with pytest.raises(nsf.NsfError) as ei:
         nsf.workspace_bytes(shape, "RA", "f64")
     assert ei.value.code == nsf.EINVAL
+
+
+def test_plane_limit(nsf):
+    # a z-plane below 2^28 points is accepted (2D, 16383 x 16384), one at
+    # 2^28 is not (the fused stage uses 32-bit byte offsets within a plane)
+    assert nsf.workspace_bytes((16383, 16384, 1), "RA", "f64") > 0
+    with pytest.raises(nsf.NsfError):
+        nsf.workspace_bytes((16384, 16384, 1), "RA", "f64")
 
 
 def test_bad_variant_and_precision_rejected(nsf):

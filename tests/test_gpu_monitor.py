@@ -100,19 +100,20 @@ def test_monitor(variant, precision, tune, oracle_run):
     assert np.all(rel_same <= bar_same), rel_same
     assert np.all(rel_oracle <= bar_oracle), rel_oracle
 
-    # monitoring does not change the trajectory. In double precision the
-    # two runs agree to round-off. In single precision the monitored kernel
-    # is a separate build whose float rounding order may differ; the two
-    # runs must agree within 4x the unmonitored run's own error against the
-    # extended-precision oracle, per field (rho w starts at zero, so its
-    # relative float error is the largest).
+    # monitoring does not change the trajectory. The monitored kernel is a
+    # separate build; where it keeps the branching form (single precision,
+    # the 8-row double-precision tile) the compiler may fuse multiply-adds
+    # differently. The two runs must agree to 1e-14 in double precision, or
+    # within 4x the unmonitored run's own error against the
+    # extended-precision oracle, per field (rho w starts near zero, so its
+    # relative rounding error is the largest).
     a = mon_solver.q.cpu().numpy().astype(np.float64)
     b = ref_solver.q.cpu().numpy().astype(np.float64)
+    own = rel_err(b, oracle_final)
     if f64:
-        assert np.all(rel_err(a, b) <= 1e-14)
+        assert np.all(rel_err(a, b) <= np.maximum(1e-14, 4 * own)), (rel_err(a, b), own)
         assert torch.equal(mon_solver.q_acc, mon_solver.q)
     else:
-        own = rel_err(b, oracle_final)
         assert np.all(rel_err(a, b) <= 4 * own), (rel_err(a, b), own)
 
 
