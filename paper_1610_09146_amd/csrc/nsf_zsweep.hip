@@ -315,20 +315,16 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
 
 constexpr int kRing = 5;
 
-// Whether the fused form keeps the per-thread halo ring of raw q in LDS
-// (each halo point fetched once per plane) or fetches every halo point twice
-// per plane from the L2 (at the leading plane for its velocity, at the
-// centre plane for its plane fields). Double-precision 32 x 8 tiles drop the
-// ring: without its LDS two workgroups fit on a CU.
+// Whether the fused form keeps a per-thread halo ring in LDS (each halo
+// point fetched once per plane: its velocity is taken at the leading plane
+// and its plane fields are parked until it is the centre plane) or fetches
+// every halo point twice per plane from the L2. Double-precision 32 x 8
+// tiles drop the ring: without its LDS two workgroups fit on a CU.
 #ifndef NSF_F64_Y8_HALO_RING
 #define NSF_F64_Y8_HALO_RING 0
 #endif
-// The single-precision monitored build drops it too: its per-thread
-// monitor slots and the ring together would exceed the LDS at which three
-// workgroups fit on a CU.
 template <typename T, int TY, bool FUSED, bool MON = false>
 constexpr bool halo_ring() {
-    if (MON && sizeof(T) == 4) return false;
     return FUSED && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
 }
 
@@ -350,7 +346,7 @@ struct PlaneLds {
 
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
 // holds 2 * kPF * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
-// 3 * 5 * NHALO values: the raw conservative values each thread loaded at
+// 3 * kPF * NHALO values: the plane fields of the raw values each thread loaded at
 // its halo point for planes z .. z+2 (a per-thread ring kept in LDS, so
 // every halo point is fetched once per plane, in the same iteration in
 // which the neighbouring tile fetches it as interior). Ends with a
@@ -458,9 +454,16 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         yw = D1(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX], k.a1[1], k.a2[1]);
     };
 
-    // per-thread halo ring (fused form): slot of plane zz, field f
+    // per-thread halo ring (fused form): slot of plane zz, plane field f
+    // (rho, E, p, T: the values the plane buffer takes at that halo point)
     auto hring = [&](int zz, int f, int h) -> T& {
-        return sH[(pmod(zz, 3) * 5 + f) * NHALO + tid + h * NT];
+        return sH[(pmod(zz, 3) * kPF + f) * NHALO + tid + h * NT];
+    };
+    auto park = [&](int zz, int h, const T f7[7]) {
+        hring(zz, 0, h) = f7[0];
+        hring(zz, 1, h) = f7[4];
+        hring(zz, 2, h) = f7[5];
+        hring(zz, 3, h) = f7[6];
     };
 
     // preamble: ring planes z0-2 .. z0+1 and their queued in-plane derivatives
@@ -483,9 +486,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     v = rp.a[2] * ir;
                     w = rp.a[3] * ir;
                     if constexpr (HR)
-                        if (s >= 2)
-#pragma unroll
-                            for (int f = 0; f < 5; ++f) hring(zz, f, h) = rp.a[f];
+                        if (s >= 2) {
+                            T f7[7];
+                            finish_p<T, FUSED>(rp, k, f7);
+                            park(zz, h, f7);
+                        }
                 } else {
                     RawV<T, FUSED> rv;
                     load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
@@ -556,18 +561,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     u = hq[h].a[1] * ir;
                     v = hq[h].a[2] * ir;
                     w = hq[h].a[3] * ir;
-                    // plane-z fields from the raw values parked two planes ago
-                    // (or fetched in the previous iteration)
-                    RawP<T, FUSED> rz;
                     if constexpr (HR) {
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) rz.a[f] = hring(z, f, h);
-#pragma unroll
-                        for (int f = 0; f < 5; ++f) hring(z + 2, f, h) = hq[h].a[f];
+                        // plane-z fields parked two planes ago; park those of z+2
+                        f7[0] = hring(z, 0, h);
+                        f7[4] = hring(z, 1, h);
+                        f7[5] = hring(z, 2, h);
+                        f7[6] = hring(z, 3, h);
+                        T g7[7];
+                        finish_p<T, FUSED>(hq[h], k, g7);
+                        park(z + 2, h, g7);
                     } else {
-                        rz = hz[h];
+                        // plane-z fields from the raw values fetched in the
+                        // previous iteration
+                        finish_p<T, FUSED>(hz[h], k, f7);
                     }
-                    finish_p<T, FUSED>(rz, k, f7);
                 } else {
                     finish_v<T, FUSED>(hv[h], u, v, w);
                     finish_p<T, FUSED>(hq[h], k, f7);
@@ -898,7 +905,7 @@ k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 15 * G::NHALO : 1];
+    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 3 * kPF * G::NHALO : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
     zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sM);
 }
@@ -915,7 +922,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
     using G = Geom<TX, TY>;
     __shared__ T sP[2 * kPF * G::NPL];
     __shared__ T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, true>() ? 15 * G::NHALO : 1];
+    __shared__ T sH[halo_ring<T, TY, true>() ? 3 * kPF * G::NHALO : 1];
     const int nb = gridDim.x;
     const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
