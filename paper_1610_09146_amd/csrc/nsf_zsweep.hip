@@ -244,8 +244,8 @@ template <typename T>
 struct Acc {
     T S0;      // sum_b D_b(rho u_b) + u_b D_b rho
     T Sm[3];   // sum_b D_b(rho u_a u_b) + u_b D_b(rho u_a)
-    T SE;      // sum_b D_b(rho E u_b) + u_b D_b(rho E)
-    T PF;      // sum_b D_b(p u_b)
+    T SE;      // sum_b D_b((rho E + 2 p) u_b) + u_b D_b(rho E): the skew
+               // convection of rho E and, by linearity, twice the pressure work
     T HEAT;    // sum_b D2_b T
     T LAP[3];  // sum_b D2_b u_a
     T D2aa[3]; // D2_a u_a
@@ -274,9 +274,9 @@ __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3]
         if (a == B) A.D2aa[a] = d2;
     }
     const T DE = D1(E[0], E[1], E[3], E[4], a1, a2);
-    const T DEu = D1(E[0] * ub[0], E[1] * ub[1], E[3] * ub[3], E[4] * ub[4], a1, a2);
-    A.SE += DEu + uc[B] * DE;
-    A.PF += D1(p[0] * ub[0], p[1] * ub[1], p[3] * ub[3], p[4] * ub[4], a1, a2);
+    // -1/2 D(E u) - D(p u) = -1/2 D((E + 2 p) u): one stencil for both fluxes
+    auto H = [&](int s) -> T { return (T(2) * p[s] + E[s]) * ub[s]; };
+    A.SE += D1(H(0), H(1), H(3), H(4), a1, a2) + uc[B] * DE;
     A.Dp[B] = D1(p[0], p[1], p[3], p[4], a1, a2);
     A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
 }
@@ -309,7 +309,7 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
             gt += A.G[a][b] * A.G[b][a];
         }
     const T work = k.inv_Re * (gg + gt - k.two_thirds * div * div);
-    R[4] = T(-0.5) * (A.SE + E * div) - A.PF + k.kappa * A.HEAT + work +
+    R[4] = T(-0.5) * (A.SE + E * div) + k.kappa * A.HEAT + work +
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
 
@@ -637,7 +637,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // (d) residual at plane z
         const T* Vc = ring(z);
         Acc<T> ac;
-        ac.S0 = ac.SE = ac.PF = ac.HEAT = T(0);
+        ac.S0 = ac.SE = ac.HEAT = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) ac.Sm[a] = ac.LAP[a] = T(0);
         const T uc[3] = {Vc[own], Vc[NPL + own], Vc[2 * NPL + own]};
