@@ -103,6 +103,7 @@ Coef<T> make_coef(const Dims& d, double Re, double Ma, double Pr, double gamma) 
     c.gm1 = (T)(gamma - 1.0);
     c.gM2 = (T)(gamma * Ma * Ma);
     c.kappa = (T)(1.0 / ((gamma - 1.0) * Ma * Ma * Pr * Re));
+    c.b0s = c.b0[0] + c.b0[1] + c.b0[2];
     return c;
 }
 template Coef<float> make_coef<float>(const Dims&, double, double, double, double);

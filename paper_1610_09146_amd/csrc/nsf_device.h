@@ -39,6 +39,7 @@ struct Coef {
     T gm1;         // gamma - 1
     T gM2;         // gamma Ma^2
     T kappa;       // 1/((gamma-1) Ma^2 Pr Re), eq (5)
+    T b0s;         // b0[0] + b0[1] + b0[2]: centre weight of the Laplacian
 };
 
 // periodic index for offsets |i - [0, n)| <= 2: one period when n >= 3, a

@@ -246,8 +246,9 @@ struct Acc {
     T Sm[3];   // sum_b D_b(rho u_a u_b) + u_b D_b(rho u_a)
     T SE;      // sum_b D_b((rho E + 2 p) u_b) + u_b D_b(rho E): the skew
                // convection of rho E and, by linearity, twice the pressure work
-    T HEAT;    // sum_b D2_b T
-    T LAP[3];  // sum_b D2_b u_a
+    T HEAT;    // sum_b D2_b T \ in the split form without the centre term:
+    T LAP[3];  // sum_b D2_b u_a / finalize adds the centre value once, times
+               //                  the sum of the three centre weights
     T D2aa[3]; // D2_a u_a
     T Dp[3];   // D_a p
     T G[3][3]; // G_ab = D_b u_a
@@ -255,8 +256,12 @@ struct Acc {
 
 // Fold direction B given stencil values (index 0..4 = offsets -2..2) of the
 // ten fields along that direction. rho/m/E/p/T arrays: f[field][5];
-// ub = velocity component B along the stencil.
-template <typename T, int B>
+// ub = velocity component B along the stencil. SPLIT: the centre terms of
+// the second differences are left to finalize, which adds them once for the
+// three directions (the recomputed-derivative forms; the stored-gradient
+// form keeps the direct sums: with the split its compiled schedule waits on
+// its gradient loads early, +29% at 512^3).
+template <typename T, int B, bool SPLIT>
 __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3][5], const T E[5],
                                          const T p[5], const T tt[5], const T vel[3][5], T a1,
                                          T a2, T b0, T b1, T b2, const T uc[3]) {
@@ -269,23 +274,31 @@ __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3]
         const T Dmu = D1(m[a][0] * ub[0], m[a][1] * ub[1], m[a][3] * ub[3], m[a][4] * ub[4], a1, a2);
         A.Sm[a] += Dmu + uc[B] * Dm;
         A.G[a][B] = D1(vel[a][0], vel[a][1], vel[a][3], vel[a][4], a1, a2);
-        const T d2 = D2(vel[a][0], vel[a][1], vel[a][2], vel[a][3], vel[a][4], b0, b1, b2);
-        A.LAP[a] += d2;
-        if (a == B) A.D2aa[a] = d2;
+        if constexpr (SPLIT) {
+            const T off = b1 * (vel[a][3] + vel[a][1]) + b2 * (vel[a][4] + vel[a][0]);
+            A.LAP[a] += off;
+            if (a == B) A.D2aa[a] = b0 * vel[a][2] + off;
+        } else {
+            const T d2 = D2(vel[a][0], vel[a][1], vel[a][2], vel[a][3], vel[a][4], b0, b1, b2);
+            A.LAP[a] += d2;
+            if (a == B) A.D2aa[a] = d2;
+        }
     }
     const T DE = D1(E[0], E[1], E[3], E[4], a1, a2);
     // -1/2 D(E u) - D(p u) = -1/2 D((E + 2 p) u): one stencil for both fluxes
     auto H = [&](int s) -> T { return (T(2) * p[s] + E[s]) * ub[s]; };
     A.SE += D1(H(0), H(1), H(3), H(4), a1, a2) + uc[B] * DE;
     A.Dp[B] = D1(p[0], p[1], p[3], p[4], a1, a2);
-    A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
+    if constexpr (SPLIT) A.HEAT += b1 * (tt[3] + tt[1]) + b2 * (tt[4] + tt[0]);
+    else A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
 }
 
 // Residual assembly; om2 receives |omega|^2 with omega = curl u from G
-// (used by the kinetic-energy / enstrophy monitor).
-template <typename T>
+// (used by the kinetic-energy / enstrophy monitor). SPLIT as in fold_dir.
+template <typename T, bool SPLIT>
 __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rho, const T m[3],
-                                         T E, const T u[3], const Coef<T>& k, T R[5], T& om2) {
+                                         T E, T t, const T u[3], const Coef<T>& k, T R[5], T& om2) {
+    const T b0s = SPLIT ? k.b0s : T(0);  // centre weight of the three second differences
     {
         const T ox = A.G[2][1] - A.G[1][2];
         const T oy = A.G[0][2] - A.G[2][0];
@@ -297,19 +310,32 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
     T V[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        V[a] = k.inv_Re * (A.LAP[a] + k.third * (A.D2aa[a] + cross[a]));
+        const T lap = SPLIT ? b0s * u[a] + A.LAP[a] : A.LAP[a];
+        V[a] = k.inv_Re * (lap + k.third * (A.D2aa[a] + cross[a]));
         R[1 + a] = T(-0.5) * (A.Sm[a] + m[a] * div) - A.Dp[a] + V[a];
     }
-    T gg = T(0), gt = T(0);
+    T ggt;
+    if constexpr (SPLIT) {
+        // sum_ab G_ab (G_ab + G_ba) = 2 sum_a G_aa^2 + sum_{a<b} (G_ab + G_ba)^2
+        const T s01 = A.G[0][1] + A.G[1][0];
+        const T s02 = A.G[0][2] + A.G[2][0];
+        const T s12 = A.G[1][2] + A.G[2][1];
+        const T dsq = A.G[0][0] * A.G[0][0] + A.G[1][1] * A.G[1][1] + A.G[2][2] * A.G[2][2];
+        ggt = T(2) * dsq + s01 * s01 + s02 * s02 + s12 * s12;
+    } else {
+        T gg = T(0), gt = T(0);
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            gg += A.G[a][b] * A.G[a][b];
-            gt += A.G[a][b] * A.G[b][a];
-        }
-    const T work = k.inv_Re * (gg + gt - k.two_thirds * div * div);
-    R[4] = T(-0.5) * (A.SE + E * div) + k.kappa * A.HEAT + work +
+            for (int b = 0; b < 3; ++b) {
+                gg += A.G[a][b] * A.G[a][b];
+                gt += A.G[a][b] * A.G[b][a];
+            }
+        ggt = gg + gt;
+    }
+    const T work = k.inv_Re * (ggt - k.two_thirds * div * div);
+    const T heat = SPLIT ? b0s * t + A.HEAT : A.HEAT;
+    R[4] = T(-0.5) * (A.SE + E * div) + k.kappa * heat + work +
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
 
@@ -661,7 +687,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 0>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
+            fold_dir<T, 0, !SS>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
         }
         {  // y
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -683,7 +709,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 1>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
+            fold_dir<T, 1, !SS>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
         }
         {  // z: register queue, velocity from the ring
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -706,7 +732,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     m[2][s] = Qz[s].m2;
                 }
             }
-            fold_dir<T, 2>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
+            fold_dir<T, 2, !SS>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
         }
         // cross derivatives sum_{c != a} D_a(G_cc)
         T cross[3];
@@ -757,7 +783,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             if constexpr (kMomFromVel)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) mc[a] = Qz[2].rho * uc[a];
-            finalize(ac, cross, Qz[2].rho, mc, Qz[2].E, uc, k, R, om2);
+            finalize<T, !SS>(ac, cross, Qz[2].rho, mc, Qz[2].E, Qz[2].t, uc, k, R, om2);
         }
         if constexpr (MON) {
             if (active) {
