@@ -229,6 +229,15 @@ __device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T a1, T a2) {
     return a1 * (p1 - m1) + a2 * (p2 - m2);
 }
 
+// First difference without its weight: D1 = a1 * D1u, since a2 = -a1 / 8
+// exactly (the two weights are 8/(12h) and -1/(12h), and scaling by a power
+// of two is exact). Sums of differences along one direction then take the
+// weight once.
+template <typename T>
+__device__ __forceinline__ T D1u(T m2, T m1, T p1, T p2) {
+    return T(-0.125) * (p2 - m2) + (p1 - m1);
+}
+
 template <typename T>
 __device__ __forceinline__ T D2(T m2, T m1, T c, T p1, T p2, T b0, T b1, T b2) {
     return b0 * c + b1 * (p1 + m1) + b2 * (p2 + m2);
@@ -256,49 +265,67 @@ struct Acc {
 
 // Fold direction B given stencil values (index 0..4 = offsets -2..2) of the
 // ten fields along that direction. rho/m/E/p/T arrays: f[field][5];
-// ub = velocity component B along the stencil. SPLIT: the centre terms of
-// the second differences are left to finalize, which adds them once for the
-// three directions (the recomputed-derivative forms; the stored-gradient
-// form keeps the direct sums: with the split its compiled schedule waits on
-// its gradient loads early, +29% at 512^3).
-template <typename T, int B, bool SPLIT>
+// ub = velocity component B along the stencil. Two rearrangements, both
+// identities of the discrete operators (only rounding changes):
+// FACT (the recomputed-derivative forms): the skew sums take the
+// first-difference weight once per direction, and D_B p is kept unweighted;
+// CENTRE (the same forms, double precision): the centre terms of the second
+// differences are left to finalize, which adds them once for the three
+// directions. In single precision that sum, b0s * T with T near 1, cancels
+// against the off-centre sums in float and the kinetic-energy change of a
+// 100-step 512^3 run drifts 3x further from the double-precision run, so
+// float keeps the per-direction second differences. The stored-gradient
+// form keeps the direct sums: with the centre terms split, its compiled
+// schedule waits on its gradient loads early (+29% at 512^3).
+template <typename T, int B, bool FACT, bool CENTRE>
 __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3][5], const T E[5],
                                          const T p[5], const T tt[5], const T vel[3][5], T a1,
                                          T a2, T b0, T b1, T b2, const T uc[3]) {
     const T* ub = vel[B];
-    const T Drho = D1(rho[0], rho[1], rho[3], rho[4], a1, a2);
-    A.S0 += D1(m[B][0], m[B][1], m[B][3], m[B][4], a1, a2) + uc[B] * Drho;
+    // skew sums: D(f u_B) + u_B D(f), with the weight a1 taken once (FACT)
+    auto dd = [&](const T f[5]) -> T {
+        if constexpr (FACT) return D1u(f[0], f[1], f[3], f[4]);
+        else return D1(f[0], f[1], f[3], f[4], a1, a2);
+    };
+    auto acc = [&](T& sum, T dfu, T df) {
+        if constexpr (FACT) sum += a1 * (dfu + uc[B] * df);
+        else sum += dfu + uc[B] * df;
+    };
+    const T Drho = dd(rho);
+    acc(A.S0, dd(m[B]), Drho);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const T Dm = D1(m[a][0], m[a][1], m[a][3], m[a][4], a1, a2);
-        const T Dmu = D1(m[a][0] * ub[0], m[a][1] * ub[1], m[a][3] * ub[3], m[a][4] * ub[4], a1, a2);
-        A.Sm[a] += Dmu + uc[B] * Dm;
+        const T Dm = dd(m[a]);
+        const T mu[5] = {m[a][0] * ub[0], m[a][1] * ub[1], T(0), m[a][3] * ub[3], m[a][4] * ub[4]};
+        acc(A.Sm[a], dd(mu), Dm);
         A.G[a][B] = D1(vel[a][0], vel[a][1], vel[a][3], vel[a][4], a1, a2);
-        if constexpr (SPLIT) {
-            const T off = b1 * (vel[a][3] + vel[a][1]) + b2 * (vel[a][4] + vel[a][0]);
-            A.LAP[a] += off;
-            if (a == B) A.D2aa[a] = b0 * vel[a][2] + off;
+        if constexpr (CENTRE) {
+            // b2 = -b1 / 16 exactly: off-centre part of D2 = b1 * offu
+            const T offu = T(-0.0625) * (vel[a][4] + vel[a][0]) + (vel[a][3] + vel[a][1]);
+            A.LAP[a] += b1 * offu;
+            if (a == B) A.D2aa[a] = b0 * vel[a][2] + b1 * offu;
         } else {
             const T d2 = D2(vel[a][0], vel[a][1], vel[a][2], vel[a][3], vel[a][4], b0, b1, b2);
             A.LAP[a] += d2;
             if (a == B) A.D2aa[a] = d2;
         }
     }
-    const T DE = D1(E[0], E[1], E[3], E[4], a1, a2);
     // -1/2 D(E u) - D(p u) = -1/2 D((E + 2 p) u): one stencil for both fluxes
     auto H = [&](int s) -> T { return (T(2) * p[s] + E[s]) * ub[s]; };
-    A.SE += D1(H(0), H(1), H(3), H(4), a1, a2) + uc[B] * DE;
-    A.Dp[B] = D1(p[0], p[1], p[3], p[4], a1, a2);
-    if constexpr (SPLIT) A.HEAT += b1 * (tt[3] + tt[1]) + b2 * (tt[4] + tt[0]);
+    const T Eu[5] = {H(0), H(1), T(0), H(3), H(4)};
+    acc(A.SE, dd(Eu), dd(E));
+    A.Dp[B] = dd(p);  // unweighted in the FACT form: finalize applies a1
+    if constexpr (CENTRE) A.HEAT += b1 * (T(-0.0625) * (tt[4] + tt[0]) + (tt[3] + tt[1]));
     else A.HEAT += D2(tt[0], tt[1], tt[2], tt[3], tt[4], b0, b1, b2);
 }
 
 // Residual assembly; om2 receives |omega|^2 with omega = curl u from G
-// (used by the kinetic-energy / enstrophy monitor). SPLIT as in fold_dir.
-template <typename T, bool SPLIT>
+// (used by the kinetic-energy / enstrophy monitor). FACT and CENTRE as in
+// fold_dir; FACT also selects the compact form of the viscous work.
+template <typename T, bool FACT, bool CENTRE>
 __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rho, const T m[3],
                                          T E, T t, const T u[3], const Coef<T>& k, T R[5], T& om2) {
-    const T b0s = SPLIT ? k.b0s : T(0);  // centre weight of the three second differences
+    const T b0s = CENTRE ? k.b0s : T(0);  // centre weight of the three second differences
     {
         const T ox = A.G[2][1] - A.G[1][2];
         const T oy = A.G[0][2] - A.G[2][0];
@@ -310,12 +337,13 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
     T V[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const T lap = SPLIT ? b0s * u[a] + A.LAP[a] : A.LAP[a];
+        const T lap = CENTRE ? b0s * u[a] + A.LAP[a] : A.LAP[a];
         V[a] = k.inv_Re * (lap + k.third * (A.D2aa[a] + cross[a]));
-        R[1 + a] = T(-0.5) * (A.Sm[a] + m[a] * div) - A.Dp[a] + V[a];
+        const T dp = FACT ? k.a1[a] * A.Dp[a] : A.Dp[a];
+        R[1 + a] = T(-0.5) * (A.Sm[a] + m[a] * div) - dp + V[a];
     }
     T ggt;
-    if constexpr (SPLIT) {
+    if constexpr (FACT) {
         // sum_ab G_ab (G_ab + G_ba) = 2 sum_a G_aa^2 + sum_{a<b} (G_ab + G_ba)^2
         const T s01 = A.G[0][1] + A.G[1][0];
         const T s02 = A.G[0][2] + A.G[2][0];
@@ -334,7 +362,7 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
         ggt = gg + gt;
     }
     const T work = k.inv_Re * (ggt - k.two_thirds * div * div);
-    const T heat = SPLIT ? b0s * t + A.HEAT : A.HEAT;
+    const T heat = CENTRE ? b0s * t + A.HEAT : A.HEAT;
     R[4] = T(-0.5) * (A.SE + E * div) + k.kappa * heat + work +
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
@@ -400,6 +428,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // that they round alike). The stored-gradient form keeps the momenta in
     // its plane fields.
     constexpr bool kMomFromVel = !SS;
+    // second-difference centre terms summed once (see fold_dir)
+    constexpr bool kCentre = !SS && sizeof(T) == 8;
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = kRing;
@@ -473,11 +503,12 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         const T* U = V;
         const T* Vv = V + NPL;
         const T* W = V + 2 * NPL;
-        const T dxu = D1(U[own - 2], U[own - 1], U[own + 1], U[own + 2], k.a1[0], k.a2[0]);
-        const T dyv = D1(Vv[own - 2 * LX], Vv[own - LX], Vv[own + LX], Vv[own + 2 * LX], k.a1[1], k.a2[1]);
-        s = dxu + dyv;
-        xw = D1(W[own - 2], W[own - 1], W[own + 1], W[own + 2], k.a1[0], k.a2[0]);
-        yw = D1(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX], k.a1[1], k.a2[1]);
+        const T dxu = D1u(U[own - 2], U[own - 1], U[own + 1], U[own + 2]);
+        const T dyv = D1u(Vv[own - 2 * LX], Vv[own - LX], Vv[own + LX], Vv[own + 2 * LX]);
+        s = k.a1[0] * dxu + k.a1[1] * dyv;
+        // unweighted: the cross terms apply the weights of both directions
+        xw = D1u(W[own - 2], W[own - 1], W[own + 1], W[own + 2]);
+        yw = D1u(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX]);
     };
 
     // per-thread halo ring (fused form): slot of plane zz, plane field f
@@ -687,7 +718,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 0, !SS>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
+            fold_dir<T, 0, !SS, kCentre>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
         }
         {  // y
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -709,7 +740,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 1, !SS>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
+            fold_dir<T, 1, !SS, kCentre>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
         }
         {  // z: register queue, velocity from the ring
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -732,7 +763,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     m[2][s] = Qz[s].m2;
                 }
             }
-            fold_dir<T, 2, !SS>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
+            fold_dir<T, 2, !SS, kCentre>(ac, rho, m, E, p, tt, vel, k.a1[2], k.a2[2], k.b0[2], k.b1[2], k.b2[2], uc);
         }
         // cross derivatives sum_{c != a} D_a(G_cc)
         T cross[3];
@@ -761,19 +792,21 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         } else {
             const T* U = Vc;
             const T* Vv = Vc + NPL;
+            // nested differences unweighted, the two weights applied once:
+            // D_x D_y v + D_z D_x w = a1x (a1y Du_x Du_y v + a1z Du_z Du_x w)
             auto dyv = [&](int mx) {
                 const int o = own + mx;
-                return D1(Vv[o - 2 * LX], Vv[o - LX], Vv[o + LX], Vv[o + 2 * LX], k.a1[1], k.a2[1]);
+                return D1u(Vv[o - 2 * LX], Vv[o - LX], Vv[o + LX], Vv[o + 2 * LX]);
             };
             auto dxu = [&](int my) {
                 const int o = own + my * LX;
-                return D1(U[o - 2], U[o - 1], U[o + 1], U[o + 2], k.a1[0], k.a2[0]);
+                return D1u(U[o - 2], U[o - 1], U[o + 1], U[o + 2]);
             };
-            const T dxdyv = D1(dyv(-2), dyv(-1), dyv(1), dyv(2), k.a1[0], k.a2[0]);
-            const T dydxu = D1(dxu(-2), dxu(-1), dxu(1), dxu(2), k.a1[1], k.a2[1]);
+            const T dxdyv = D1u(dyv(-2), dyv(-1), dyv(1), dyv(2));
+            const T dydxu = D1u(dxu(-2), dxu(-1), dxu(1), dxu(2));
             const T a1z = k.a1[2], a2z = k.a2[2];
-            cross[0] = dxdyv + D1(Xw[0], Xw[1], Xw[3], Xw[4], a1z, a2z);
-            cross[1] = dydxu + D1(Yw[0], Yw[1], Yw[3], Yw[4], a1z, a2z);
+            cross[0] = k.a1[0] * (k.a1[1] * dxdyv + a1z * D1u(Xw[0], Xw[1], Xw[3], Xw[4]));
+            cross[1] = k.a1[1] * (k.a1[0] * dydxu + a1z * D1u(Yw[0], Yw[1], Yw[3], Yw[4]));
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], a1z, a2z);
         }
         T R[5];
@@ -783,7 +816,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             if constexpr (kMomFromVel)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) mc[a] = Qz[2].rho * uc[a];
-            finalize<T, !SS>(ac, cross, Qz[2].rho, mc, Qz[2].E, Qz[2].t, uc, k, R, om2);
+            finalize<T, !SS, kCentre>(ac, cross, Qz[2].rho, mc, Qz[2].E, Qz[2].t, uc, k, R, om2);
         }
         if constexpr (MON) {
             if (active) {
