@@ -55,6 +55,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_view(const void* base, u
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
                                              kRsrcWord3);
 }
+// cached load of a field value (the q planes are re-read by neighbouring tiles)
+template <typename T>
+__device__ __forceinline__ T plane_load(__amdgpu_buffer_rsrc_t v, uint32_t off) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v, off, 0, 0));
+    else
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v, off, 0, 0));
+}
 __device__ __forceinline__ double view_load(__amdgpu_buffer_rsrc_t v, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v, off, 0, kPolicy));
 }
@@ -465,6 +473,12 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         hcol[h] = (size_t)pmod(y0 + hy - 2, d.ny) * d.nx + pmod(x0 + hx - 2, d.nx);
     }
     auto poff = [&](int z) { return (size_t)pmod(z, d.nz) * plane; };
+    // plane-view byte offsets of the own column and the halo points
+    const uint32_t pq = (uint32_t)(plane * sizeof(T));
+    const uint32_t colq = (uint32_t)(col * sizeof(T));
+    uint32_t hcolq[HPT];
+#pragma unroll
+    for (int h = 0; h < HPT; ++h) hcolq[h] = (uint32_t)(hcol[h] * sizeof(T));
     auto ring = [&](int z) { return sV + pmod(z, RING) * 3 * NPL; };
     // in-plane offsets of the own column's x and y neighbours at -2, -1, +1, +2
     size_t xnb[4], ynb[4];
@@ -649,19 +663,41 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     Pz[6 * NPL + hidx[h]] = f7[3];
                 }
             }
-        // (b) prefetch the next iteration's loads
+        // (b) prefetch the next iteration's loads. The lean form loads
+        // through plane views (one 32-bit offset per lane instead of a 64-bit
+        // address per field) and on every lane: a halo slot past the end has
+        // the wrapped address of the tile's corner and is left unused, since a
+        // branch here would make the wait for these loads also wait for this
+        // plane's stores.
         Raw<T, FUSED> nxt;
-        load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+        if constexpr (kLean) {
+            const size_t z3 = poff(z + 3);
+#pragma unroll
+            for (int f = 0; f < 5; ++f) nxt.q[f] = plane_load<T>(plane_view(A.q + f * n + z3, pq), colq);
+#pragma unroll
+            for (int h = 0; h < HPT; ++h)
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+                    hq[h].a[f] = plane_load<T>(plane_view(A.q + f * n + z3, pq), hcolq[h]);
+            if constexpr (!HR) {
+                const size_t z1p = poff(z + 1);
+#pragma unroll
+                for (int h = 0; h < HPT; ++h)
+#pragma unroll
+                    for (int f = 0; f < 5; ++f)
+                        hz[h].a[f] = plane_load<T>(plane_view(A.q + f * n + z1p, pq), hcolq[h]);
+            }
+        } else {
+            load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+        }
         T gnx[SS ? 2 : 1];
         if constexpr (SS) {
             gnx[0] = A.grad[0 * n + poff(z + 3) + col];
             gnx[1] = A.grad[4 * n + poff(z + 3) + col];
         }
-        // (lean form: a halo slot past the end loads the wrapped address of
-        // the tile's corner and leaves it unused)
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
-            if (kLean || hval[h]) {
+            if (!kLean && hval[h]) {
                 if constexpr (FUSED) {
                     load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
                     if constexpr (!HR)
@@ -844,13 +880,13 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
                 for (int f = 0; f < 5; ++f) acc[f] = view_load(plane_view(A.qacc + f * n + zo, pb), off);
             }
+            // the last stage's output is q_acc itself: the same fma with B dt
+            const double out_dt = A.last ? A.b_dt : A.a_dt;
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
                 const double rr = (double)R[f];
-                const double na = fma(A.b_dt, rr, acc[f]);
-                view_store(na, plane_view(A.qacc + f * n + zo, pb), off);
-                view_store(A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]),
-                           plane_view(A.qout + f * n + zo, pbT), offT);
+                view_store(fma(A.b_dt, rr, acc[f]), plane_view(A.qacc + f * n + zo, pb), off);
+                view_store((T)fma(out_dt, rr, acc[f]), plane_view(A.qout + f * n + zo, pbT), offT);
             }
         } else if (active) {
             if constexpr (FUSED) {
@@ -858,12 +894,12 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
                     for (int f = 0; f < 5; ++f) acc[f] = stream_load(A.qacc + f * n + oidx);
                 }
+                const double out_dt = A.last ? A.b_dt : A.a_dt;
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
                     const double rr = (double)R[f];
-                    const double na = fma(A.b_dt, rr, acc[f]);
-                    stream_store(na, A.qacc + f * n + oidx);
-                    stream_store(A.last ? (T)na : (T)fma(A.a_dt, rr, acc[f]), A.qout + f * n + oidx);
+                    stream_store(fma(A.b_dt, rr, acc[f]), A.qacc + f * n + oidx);
+                    stream_store((T)fma(out_dt, rr, acc[f]), A.qout + f * n + oidx);
                 }
             } else {
 #pragma unroll
