@@ -97,6 +97,10 @@ struct Geom {
     static constexpr int NPL = LX * LY;
     static constexpr int NHALO = NPL - NT;
     static constexpr int HPT = (NHALO + NT - 1) / NT;
+    // cross-derivative ring: D_y v on the tile rows with the x halo, D_x u on
+    // the tile columns with the y halo
+    static constexpr int DYN = LX * TY, DXN = TX * LY, DSZ = DYN + DXN;
+    static constexpr int DHALO = 4 * TY + 4 * TX;  // halo points of the two
 };
 
 // Halo position h (0 .. NHALO-1) -> LDS coordinates: two full rows below,
@@ -237,6 +241,15 @@ __device__ __forceinline__ T D1(T m2, T m1, T p1, T p2, T a1, T a2) {
     return a1 * (p1 - m1) + a2 * (p2 - m2);
 }
 
+// a * b + c with one rounding, whatever the surrounding code: where the same
+// value is formed at several call sites and must agree bitwise, the choice
+// of which product the compiler fuses is not left to it
+template <typename T>
+__device__ __forceinline__ T fmadd(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
 // First difference without its weight: D1 = a1 * D1u, since a2 = -a1 / 8
 // exactly (the two weights are 8/(12h) and -1/(12h), and scaling by a power
 // of two is exact). Sums of differences along one direction then take the
@@ -375,7 +388,28 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
 
-constexpr int kRing = 5;
+// Whether the tile keeps unweighted D_y v and D_x u of the last three
+// leading planes in LDS, so that the nested cross differences D_x D_y v and
+// D_y D_x u read four values each instead of forming sixteen-point stencils:
+// the double-precision 16-row tiles of the recomputed-derivative forms,
+// whose stage is bound by its arithmetic (-5.6% on the fused 512^3 stage).
+// Not the 8-row tile, whose LDS must stay under half the CU's for two
+// workgroups, and not single precision, whose stage is bound by memory
+// (no gain measured, +2% on its monitored build).
+template <typename T, int TY, bool SS>
+constexpr bool d_ring() {
+    return !SS && sizeof(T) == 8 && TY == 16;
+}
+
+// Velocity ring slots. Five, or four where the fused tile keeps the D ring
+// and needs the room: then the slot of the leading plane z+2 is that of
+// z-2, whose in-plane readers (it was the centre plane two barriers ago)
+// are done, and its own column, which the z fold still reads, is copied to
+// registers first.
+template <typename T, int TY, bool FUSED, bool SS>
+constexpr int ring_slots() {
+    return FUSED && d_ring<T, TY, SS>() ? 4 : 5;
+}
 
 // Whether the fused form keeps a per-thread halo ring in LDS (each halo
 // point fetched once per plane: its velocity is taken at the leading plane
@@ -407,15 +441,17 @@ struct PlaneLds {
 };
 
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
-// holds 2 * kPF * NPL and sV kRing * 3 * NPL values; in the fused form sH holds
-// 3 * kPF * NHALO values: the plane fields of the raw values each thread loaded at
-// its halo point for planes z .. z+2 (a per-thread ring kept in LDS, so
+// holds 2 * kPF * NPL and sV ring_slots * 3 * NPL values; in the fused form sH
+// holds 2 * kPF * NHALO values: the plane fields of the raw values each thread
+// loaded at its halo point for planes z+1, z+2 (a per-thread ring kept in LDS,
+// two slots since each thread reads plane z's before parking z+2's; so
 // every halo point is fetched once per plane, in the same iteration in
 // which the neighbouring tile fetches it as interior). Ends with a
 // barrier, so the caller may reuse the LDS for another tile right away.
 template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
                                             T* __restrict__ sV, T* __restrict__ sH,
+                                            T* __restrict__ sD,
                                             double2* __restrict__ sM = nullptr) {
     static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
     static_assert(!MON || FUSED, "the monitor is part of the fused stage");
@@ -440,7 +476,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     constexpr bool kCentre = !SS && sizeof(T) == 8;
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
-    constexpr int RING = kRing;
+    constexpr int RING = ring_slots<T, TY, FUSED, SS>();
+    constexpr bool DR = d_ring<T, TY, SS>();
 
     const Dims d = A.d;
     const Coef<T> k = A.k;
@@ -472,6 +509,27 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         hidx[h] = hy * LX + hx;
         hcol[h] = (size_t)pmod(y0 + hy - 2, d.ny) * d.nx + pmod(x0 + hx - 2, d.nx);
     }
+    // D ring: the last DHALO threads also form D_y v on the x-halo columns
+    // (4 x TY points) and D_x u on the y-halo rows (TX x 4 points)
+    int dq = -1, dsrc = 0, ddst = 0;
+    if constexpr (DR) {
+        const int i = tid - (NT - G::DHALO);
+        if (i >= 0 && i < 4 * TY) {
+            const int c = i / TY, r = i % TY;
+            const int hx = c < 2 ? c : TX + c;
+            dq = 0;
+            dsrc = (r + 2) * LX + hx;
+            ddst = r * LX + hx;
+        } else if (i >= 4 * TY) {
+            const int j = i - 4 * TY;
+            const int rr = j / TX, c = j % TX;
+            const int hy = rr < 2 ? rr : TY + rr;
+            dq = 1;
+            dsrc = hy * LX + c + 2;
+            ddst = G::DYN + hy * TX + c;
+        }
+    }
+    auto dslot = [&](int z) { return sD + pmod(z, 3) * G::DSZ; };
     auto poff = [&](int z) { return (size_t)pmod(z, d.nz) * plane; };
     // plane-view byte offsets of the own column and the halo points
     const uint32_t pq = (uint32_t)(plane * sizeof(T));
@@ -513,13 +571,32 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Xw[s] = A.grad[4 * n + poff(z0 - 2 + s) + col];
         }
     }
-    auto leading = [&](const T* V, T& s, T& xw, T& yw) {
+    auto leading = [&](const T* V, T& s, T& xw, T& yw, int zz, bool keepD) {
         const T* U = V;
         const T* Vv = V + NPL;
         const T* W = V + 2 * NPL;
         const T dxu = D1u(U[own - 2], U[own - 1], U[own + 1], U[own + 2]);
         const T dyv = D1u(Vv[own - 2 * LX], Vv[own - LX], Vv[own + LX], Vv[own + 2 * LX]);
-        s = k.a1[0] * dxu + k.a1[1] * dyv;
+        if constexpr (DR) {
+            // unweighted D_y v and D_x u of this plane, for its cross terms two
+            // iterations on (written after the barrier, read after the barrier
+            // two planes later; the slot it replaces was read last plane)
+            if (keepD) {
+                T* D = dslot(zz);
+                D[ly * LX + lx + 2] = dyv;
+                D[G::DYN + (ly + 2) * TX + lx] = dxu;
+                if (dq == 0) {
+                    const T* f = Vv + dsrc;
+                    D[ddst] = D1u(f[-2 * LX], f[-LX], f[LX], f[2 * LX]);
+                } else if (dq == 1) {
+                    const T* f = U + dsrc;
+                    D[ddst] = D1u(f[-2], f[-1], f[1], f[2]);
+                }
+            }
+        }
+        // (queued per plane: on a single-plane grid the z difference of the
+        // queue is then exactly zero)
+        s = fmadd(k.a1[0], dxu, k.a1[1] * dyv);
         // unweighted: the cross terms apply the weights of both directions
         xw = D1u(W[own - 2], W[own - 1], W[own + 1], W[own + 2]);
         yw = D1u(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX]);
@@ -528,7 +605,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // per-thread halo ring (fused form): slot of plane zz, plane field f
     // (rho, E, p, T: the values the plane buffer takes at that halo point)
     auto hring = [&](int zz, int f, int h) -> T& {
-        return sH[(pmod(zz, 3) * kPF + f) * NHALO + tid + h * NT];
+        return sH[(pmod(zz, 2) * kPF + f) * NHALO + tid + h * NT];
     };
     auto park = [&](int zz, int h, const T f7[7]) {
         hring(zz, 0, h) = f7[0];
@@ -572,7 +649,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 V[2 * NPL + hidx[h]] = w;
             }
         __syncthreads();
-        if constexpr (!SS) leading(V, Xs[s], Xw[s], Yw[s]);
+        if constexpr (!SS) leading(V, Xs[s], Xw[s], Yw[s], zz, s >= 2);
     }
 
     // prefetched halo values for the first iteration: fused form, raw q of
@@ -602,10 +679,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     if constexpr (kLdsMon) sM[tid] = make_double2(0.0, 0.0);
 
     for (int z = z0; z < z1; ++z) {
-        // (a) LDS: ring slot of plane z+2 (velocity) and the plane-z fields;
-        // the slot of plane z+2 last held plane z-3, whose readers finished
-        // before the barrier that ended the previous iteration
+        // (a) LDS: ring slot of plane z+2 (velocity) and the plane-z fields.
+        // The slot of plane z+2 last held plane z+2-RING, whose in-plane
+        // readers are done (see ring_slots); with four slots that is plane
+        // z-2, and its own column, still needed by the z fold, is kept first
         T* Vl = ring(z + 2);
+        T vm2[3];
+        if constexpr (RING == 4) {
+            vm2[0] = Vl[own];
+            vm2[1] = Vl[NPL + own];
+            vm2[2] = Vl[2 * NPL + own];
+        }
         Vl[own] = unew[0];
         Vl[NPL + own] = unew[1];
         Vl[2 * NPL + own] = unew[2];
@@ -725,7 +809,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         __syncthreads();
 
         // (c) leading-plane in-plane derivatives for the z cross terms
-        if constexpr (!SS) leading(Vl, Xs[4], Xw[4], Yw[4]);
+        if constexpr (!SS) leading(Vl, Xs[4], Xw[4], Yw[4], z + 2, true);
 
         // (d) residual at plane z
         const T* Vc = ring(z);
@@ -787,9 +871,14 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 E[s] = Qz[s].E;
                 p[s] = Qz[s].p;
                 tt[s] = Qz[s].t;
-                vel[0][s] = Vs[own];
-                vel[1][s] = Vs[NPL + own];
-                vel[2][s] = Vs[2 * NPL + own];
+                if (RING == 4 && s == 0) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) vel[a][0] = vm2[a];
+                } else {
+                    vel[0][s] = Vs[own];
+                    vel[1][s] = Vs[NPL + own];
+                    vel[2][s] = Vs[2 * NPL + own];
+                }
                 if constexpr (kMomFromVel) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
@@ -838,8 +927,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 const int o = own + my * LX;
                 return D1u(U[o - 2], U[o - 1], U[o + 1], U[o + 2]);
             };
-            const T dxdyv = D1u(dyv(-2), dyv(-1), dyv(1), dyv(2));
-            const T dydxu = D1u(dxu(-2), dxu(-1), dxu(1), dxu(2));
+            T dxdyv, dydxu;
+            if constexpr (DR) {
+                // from the D ring: D_y v along the row, D_x u along the column
+                const T* Dy = dslot(z) + ly * LX + lx;
+                const T* Dx = dslot(z) + G::DYN + ly * TX + lx;
+                dxdyv = D1u(Dy[0], Dy[1], Dy[3], Dy[4]);
+                dydxu = D1u(Dx[0], Dx[TX], Dx[3 * TX], Dx[4 * TX]);
+            } else {
+                dxdyv = D1u(dyv(-2), dyv(-1), dyv(1), dyv(2));
+                dydxu = D1u(dxu(-2), dxu(-1), dxu(1), dxu(2));
+            }
             const T a1z = k.a1[2], a2z = k.a2[2];
             cross[0] = k.a1[0] * (k.a1[1] * dxdyv + a1z * D1u(Xw[0], Xw[1], Xw[3], Xw[4]));
             cross[1] = k.a1[1] * (k.a1[0] * dydxu + a1z * D1u(Yw[0], Yw[1], Yw[3], Yw[4]));
@@ -999,10 +1097,11 @@ __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
 k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
-    __shared__ __attribute__((aligned(16))) T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 3 * kPF * G::NHALO : 1];
+    __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, FUSED, SS>() * 3 * G::NPL];
+    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 2 * kPF * G::NHALO : 1];
+    __shared__ T sD[d_ring<T, TY, SS>() ? 3 * G::DSZ : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
-    zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sM);
+    zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sD, sM);
 }
 
 // Persistent batched stage kernel: every workgroup walks the work list of
@@ -1016,8 +1115,9 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
            int stage) {
     using G = Geom<TX, TY>;
     __shared__ T sP[2 * kPF * G::NPL];
-    __shared__ T sV[kRing * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, true>() ? 3 * kPF * G::NHALO : 1];
+    __shared__ T sV[ring_slots<T, TY, true, false>() * 3 * G::NPL];
+    __shared__ T sH[halo_ring<T, TY, true>() ? 2 * kPF * G::NHALO : 1];
+    __shared__ T sD[d_ring<T, TY, false>() ? 3 * G::DSZ : 1];
     const int nb = gridDim.x;
     const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
@@ -1043,7 +1143,7 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.mpart = nullptr;
         A.tiles_x = bd.tiles_x;
         A.tiles_y = bd.tiles_y;
-        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV, sH);
+        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV, sH, sD);
     }
 }
 
