@@ -298,7 +298,9 @@ struct Acc {
 // float keeps the per-direction second differences. The stored-gradient
 // form keeps the direct sums: with the centre terms split, its compiled
 // schedule waits on its gradient loads early (+29% at 512^3).
-template <typename T, int B, bool FACT, bool CENTRE>
+// GSKIP: bit a set leaves G[a][B] to the caller, which has it from earlier
+// work on the plane (see the tile loop).
+template <typename T, int B, bool FACT, bool CENTRE, int GSKIP = 0>
 __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3][5], const T E[5],
                                          const T p[5], const T tt[5], const T vel[3][5], T a1,
                                          T a2, T b0, T b1, T b2, const T uc[3]) {
@@ -319,7 +321,7 @@ __device__ __forceinline__ void fold_dir(Acc<T>& A, const T rho[5], const T m[3]
         const T Dm = dd(m[a]);
         const T mu[5] = {m[a][0] * ub[0], m[a][1] * ub[1], T(0), m[a][3] * ub[3], m[a][4] * ub[4]};
         acc(A.Sm[a], dd(mu), Dm);
-        A.G[a][B] = D1(vel[a][0], vel[a][1], vel[a][3], vel[a][4], a1, a2);
+        if (!((GSKIP >> a) & 1)) A.G[a][B] = D1(vel[a][0], vel[a][1], vel[a][3], vel[a][4], a1, a2);
         if constexpr (CENTRE) {
             // b2 = -b1 / 16 exactly: off-centre part of D2 = b1 * offu
             const T offu = T(-0.0625) * (vel[a][4] + vel[a][0]) + (vel[a][3] + vel[a][1]);
@@ -478,6 +480,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = ring_slots<T, TY, FUSED, SS>();
     constexpr bool DR = d_ring<T, TY, SS>();
+    // velocity gradients of the centre plane that earlier work already holds
+    // unweighted: D_x w and D_y w in the z-cross queues (formed when the plane
+    // led), D_x u and D_y v in the D ring; the x and y folds skip them
+    constexpr int kGskipX = SS ? 0 : (DR ? 0b101 : 0b100);
+    constexpr int kGskipY = SS ? 0 : (DR ? 0b110 : 0b100);
 
     const Dims d = A.d;
     const Coef<T> k = A.k;
@@ -838,7 +845,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 0, !SS, kCentre>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
+            fold_dir<T, 0, !SS, kCentre, kGskipX>(ac, rho, m, E, p, tt, vel, k.a1[0], k.a2[0], k.b0[0], k.b1[0], k.b2[0], uc);
         }
         {  // y
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -860,7 +867,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
                 }
             }
-            fold_dir<T, 1, !SS, kCentre>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
+            fold_dir<T, 1, !SS, kCentre, kGskipY>(ac, rho, m, E, p, tt, vel, k.a1[1], k.a2[1], k.b0[1], k.b1[1], k.b2[1], uc);
         }
         {  // z: register queue, velocity from the ring
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
@@ -934,11 +941,15 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 const T* Dx = dslot(z) + G::DYN + ly * TX + lx;
                 dxdyv = D1u(Dy[0], Dy[1], Dy[3], Dy[4]);
                 dydxu = D1u(Dx[0], Dx[TX], Dx[3 * TX], Dx[4 * TX]);
+                ac.G[0][0] = k.a1[0] * Dx[2 * TX];
+                ac.G[1][1] = k.a1[1] * Dy[2];
             } else {
                 dxdyv = D1u(dyv(-2), dyv(-1), dyv(1), dyv(2));
                 dydxu = D1u(dxu(-2), dxu(-1), dxu(1), dxu(2));
             }
             const T a1z = k.a1[2], a2z = k.a2[2];
+            ac.G[2][0] = k.a1[0] * Xw[2];
+            ac.G[2][1] = k.a1[1] * Yw[2];
             cross[0] = k.a1[0] * (k.a1[1] * dxdyv + a1z * D1u(Xw[0], Xw[1], Xw[3], Xw[4]));
             cross[1] = k.a1[1] * (k.a1[0] * dydxu + a1z * D1u(Yw[0], Yw[1], Yw[3], Yw[4]));
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], a1z, a2z);
