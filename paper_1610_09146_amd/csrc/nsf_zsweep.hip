@@ -429,9 +429,9 @@ constexpr bool halo_ring() {
 // Plane fields kept in LDS with their halo: rho, E, p, T (momentum at a
 // neighbour is rebuilt as rho * u from the velocity ring). Two buffers
 // alternate by plane parity, so the writes of plane z+1 never meet the reads
-// of plane z and one barrier per plane suffices: the ring slot a plane
-// recycles (z+3, the slot of z-2) is read at that point only for the own
-// column, by the thread that writes it.
+// of plane z and one barrier per plane suffices: the velocity-ring slot a
+// plane recycles is read at that point only for the own column, by the
+// thread that writes it (see ring_slots).
 constexpr int kPF = 4;
 // The stored-gradient form runs at the register limit; rebuilding momentum
 // would spill there, so it keeps seven plane fields in one buffer (momentum
@@ -502,9 +502,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     const int gi = x0 + lx, gj = y0 + ly;
     const bool active = gi < d.nx && gj < d.ny;
     const size_t col = (size_t)pmod(gj, d.ny) * d.nx + pmod(gi, d.nx);
-    const int own = (ly + 2) * LX + (lx + 2);
+    // LDS planes of the recomputed-derivative forms are stored row by row
+    // with the fields of a row side by side ([row][field][column]): all
+    // fields of a row then lie within the reach of one ds_read2 base (2040
+    // bytes), where field-major planes need a base per field (-1.8% on the
+    // FP64 and -4.6% on the FP32 fused stage). The stored-gradient form keeps
+    // field-major planes ([field][row][column]): interleaved, its compiled
+    // schedule ran 20% slower. RS*: row strides; FO*: field offsets.
+    constexpr int PF = PlaneLds<SS>::kFields;
+    constexpr int RSV = SS ? LX : 3 * LX, RSP = SS ? LX : PF * LX;
+    constexpr int FOV = SS ? NPL : LX, FOP = SS ? NPL : LX;
+    const int ownV = (ly + 2) * RSV + (lx + 2);
+    const int ownP = (ly + 2) * RSP + (lx + 2);
 
-    int hidx[HPT];
+    int hidxV[HPT], hidxP[HPT];
     size_t hcol[HPT];
     bool hval[HPT];
 #pragma unroll
@@ -513,7 +524,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         hval[h] = hh < NHALO;
         int hx = 0, hy = 0;
         if (hval[h]) halo_pos<TX, TY>(hh, hx, hy);
-        hidx[h] = hy * LX + hx;
+        hidxV[h] = hy * RSV + hx;
+        hidxP[h] = hy * RSP + hx;
         hcol[h] = (size_t)pmod(y0 + hy - 2, d.ny) * d.nx + pmod(x0 + hx - 2, d.nx);
     }
     // D ring: the last DHALO threads also form D_y v on the x-halo columns
@@ -525,14 +537,14 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             const int c = i / TY, r = i % TY;
             const int hx = c < 2 ? c : TX + c;
             dq = 0;
-            dsrc = (r + 2) * LX + hx;
+            dsrc = (r + 2) * RSV + hx;
             ddst = r * LX + hx;
         } else if (i >= 4 * TY) {
             const int j = i - 4 * TY;
             const int rr = j / TX, c = j % TX;
             const int hy = rr < 2 ? rr : TY + rr;
             dq = 1;
-            dsrc = hy * LX + c + 2;
+            dsrc = hy * RSV + c + 2;
             ddst = G::DYN + hy * TX + c;
         }
     }
@@ -580,10 +592,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     }
     auto leading = [&](const T* V, T& s, T& xw, T& yw, int zz, bool keepD) {
         const T* U = V;
-        const T* Vv = V + NPL;
-        const T* W = V + 2 * NPL;
-        const T dxu = D1u(U[own - 2], U[own - 1], U[own + 1], U[own + 2]);
-        const T dyv = D1u(Vv[own - 2 * LX], Vv[own - LX], Vv[own + LX], Vv[own + 2 * LX]);
+        const T* Vv = V + FOV;
+        const T* W = V + 2 * FOV;
+        const T dxu = D1u(U[ownV - 2], U[ownV - 1], U[ownV + 1], U[ownV + 2]);
+        const T dyv = D1u(Vv[ownV - 2 * RSV], Vv[ownV - RSV], Vv[ownV + RSV], Vv[ownV + 2 * RSV]);
         if constexpr (DR) {
             // unweighted D_y v and D_x u of this plane, for its cross terms two
             // iterations on (written after the barrier, read after the barrier
@@ -594,7 +606,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 D[G::DYN + (ly + 2) * TX + lx] = dxu;
                 if (dq == 0) {
                     const T* f = Vv + dsrc;
-                    D[ddst] = D1u(f[-2 * LX], f[-LX], f[LX], f[2 * LX]);
+                    D[ddst] = D1u(f[-2 * RSV], f[-RSV], f[RSV], f[2 * RSV]);
                 } else if (dq == 1) {
                     const T* f = U + dsrc;
                     D[ddst] = D1u(f[-2], f[-1], f[1], f[2]);
@@ -605,8 +617,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // queue is then exactly zero)
         s = fmadd(k.a1[0], dxu, k.a1[1] * dyv);
         // unweighted: the cross terms apply the weights of both directions
-        xw = D1u(W[own - 2], W[own - 1], W[own + 1], W[own + 2]);
-        yw = D1u(W[own - 2 * LX], W[own - LX], W[own + LX], W[own + 2 * LX]);
+        xw = D1u(W[ownV - 2], W[ownV - 1], W[ownV + 1], W[ownV + 2]);
+        yw = D1u(W[ownV - 2 * RSV], W[ownV - RSV], W[ownV + RSV], W[ownV + 2 * RSV]);
     };
 
     // per-thread halo ring (fused form): slot of plane zz, plane field f
@@ -626,9 +638,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     for (int s = 0; s < 4; ++s) {
         const int zz = z0 - 2 + s;
         T* V = ring(zz);
-        V[own] = uvw[s][0];
-        V[NPL + own] = uvw[s][1];
-        V[2 * NPL + own] = uvw[s][2];
+        V[ownV] = uvw[s][0];
+        V[FOV + ownV] = uvw[s][1];
+        V[2 * FOV + ownV] = uvw[s][2];
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
@@ -651,9 +663,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
                     finish_v<T, FUSED>(rv, u, v, w);
                 }
-                V[hidx[h]] = u;
-                V[NPL + hidx[h]] = v;
-                V[2 * NPL + hidx[h]] = w;
+                V[hidxV[h]] = u;
+                V[FOV + hidxV[h]] = v;
+                V[2 * FOV + hidxV[h]] = w;
             }
         __syncthreads();
         if constexpr (!SS) leading(V, Xs[s], Xw[s], Yw[s], zz, s >= 2);
@@ -693,24 +705,23 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         T* Vl = ring(z + 2);
         T vm2[3];
         if constexpr (RING == 4) {
-            vm2[0] = Vl[own];
-            vm2[1] = Vl[NPL + own];
-            vm2[2] = Vl[2 * NPL + own];
+            vm2[0] = Vl[ownV];
+            vm2[1] = Vl[FOV + ownV];
+            vm2[2] = Vl[2 * FOV + ownV];
         }
-        Vl[own] = unew[0];
-        Vl[NPL + own] = unew[1];
-        Vl[2 * NPL + own] = unew[2];
-        constexpr int PF = PlaneLds<SS>::kFields;
+        Vl[ownV] = unew[0];
+        Vl[FOV + ownV] = unew[1];
+        Vl[2 * FOV + ownV] = unew[2];
         T* Pz = sP + (PlaneLds<SS>::kBuffers == 2 ? (z & 1) * PF * NPL : 0);  // plane z
         // field slots: rho, E, p, T, then (stored-gradient form) m0, m1, m2
-        Pz[own] = Qz[2].rho;
-        Pz[NPL + own] = Qz[2].E;
-        Pz[2 * NPL + own] = Qz[2].p;
-        Pz[3 * NPL + own] = Qz[2].t;
+        Pz[ownP] = Qz[2].rho;
+        Pz[FOP + ownP] = Qz[2].E;
+        Pz[2 * FOP + ownP] = Qz[2].p;
+        Pz[3 * FOP + ownP] = Qz[2].t;
         if constexpr (PF == 7) {
-            Pz[4 * NPL + own] = Qz[2].m0;
-            Pz[5 * NPL + own] = Qz[2].m1;
-            Pz[6 * NPL + own] = Qz[2].m2;
+            Pz[4 * FOP + ownP] = Qz[2].m0;
+            Pz[5 * FOP + ownP] = Qz[2].m1;
+            Pz[6 * FOP + ownP] = Qz[2].m2;
         }
 #pragma unroll
         for (int h = 0; h < HPT; ++h)
@@ -741,17 +752,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     finish_v<T, FUSED>(hv[h], u, v, w);
                     finish_p<T, FUSED>(hq[h], k, f7);
                 }
-                Vl[hidx[h]] = u;
-                Vl[NPL + hidx[h]] = v;
-                Vl[2 * NPL + hidx[h]] = w;
-                Pz[hidx[h]] = f7[0];
-                Pz[NPL + hidx[h]] = f7[4];
-                Pz[2 * NPL + hidx[h]] = f7[5];
-                Pz[3 * NPL + hidx[h]] = f7[6];
+                Vl[hidxV[h]] = u;
+                Vl[FOV + hidxV[h]] = v;
+                Vl[2 * FOV + hidxV[h]] = w;
+                Pz[hidxP[h]] = f7[0];
+                Pz[FOP + hidxP[h]] = f7[4];
+                Pz[2 * FOP + hidxP[h]] = f7[5];
+                Pz[3 * FOP + hidxP[h]] = f7[6];
                 if constexpr (PF == 7) {
-                    Pz[4 * NPL + hidx[h]] = f7[1];
-                    Pz[5 * NPL + hidx[h]] = f7[2];
-                    Pz[6 * NPL + hidx[h]] = f7[3];
+                    Pz[4 * FOP + hidxP[h]] = f7[1];
+                    Pz[5 * FOP + hidxP[h]] = f7[2];
+                    Pz[6 * FOP + hidxP[h]] = f7[3];
                 }
             }
         // (b) prefetch the next iteration's loads. The lean form loads
@@ -824,22 +835,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         ac.S0 = ac.SE = ac.HEAT = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) ac.Sm[a] = ac.LAP[a] = T(0);
-        const T uc[3] = {Vc[own], Vc[NPL + own], Vc[2 * NPL + own]};
+        const T uc[3] = {Vc[ownV], Vc[FOV + ownV], Vc[2 * FOV + ownV]};
         {  // x
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
-                const int o = own + s - 2;
+                const int o = ownP + s - 2, ov = ownV + s - 2;
                 rho[s] = Pz[o];
-                E[s] = Pz[NPL + o];
-                p[s] = Pz[2 * NPL + o];
-                tt[s] = Pz[3 * NPL + o];
-                vel[0][s] = Vc[o];
-                vel[1][s] = Vc[NPL + o];
-                vel[2][s] = Vc[2 * NPL + o];
+                E[s] = Pz[FOP + o];
+                p[s] = Pz[2 * FOP + o];
+                tt[s] = Pz[3 * FOP + o];
+                vel[0][s] = Vc[ov];
+                vel[1][s] = Vc[FOV + ov];
+                vel[2][s] = Vc[2 * FOV + ov];
                 if constexpr (PF == 7) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * NPL + o];
+                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * FOP + o];
                 } else {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
@@ -851,17 +862,17 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
 #pragma unroll
             for (int s = 0; s < 5; ++s) {
-                const int o = own + (s - 2) * LX;
+                const int o = ownP + (s - 2) * RSP, ov = ownV + (s - 2) * RSV;
                 rho[s] = Pz[o];
-                E[s] = Pz[NPL + o];
-                p[s] = Pz[2 * NPL + o];
-                tt[s] = Pz[3 * NPL + o];
-                vel[0][s] = Vc[o];
-                vel[1][s] = Vc[NPL + o];
-                vel[2][s] = Vc[2 * NPL + o];
+                E[s] = Pz[FOP + o];
+                p[s] = Pz[2 * FOP + o];
+                tt[s] = Pz[3 * FOP + o];
+                vel[0][s] = Vc[ov];
+                vel[1][s] = Vc[FOV + ov];
+                vel[2][s] = Vc[2 * FOV + ov];
                 if constexpr (PF == 7) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * NPL + o];
+                    for (int a = 0; a < 3; ++a) m[a][s] = Pz[(4 + a) * FOP + o];
                 } else {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) m[a][s] = rho[s] * vel[a][s];
@@ -882,9 +893,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 #pragma unroll
                     for (int a = 0; a < 3; ++a) vel[a][0] = vm2[a];
                 } else {
-                    vel[0][s] = Vs[own];
-                    vel[1][s] = Vs[NPL + own];
-                    vel[2][s] = Vs[2 * NPL + own];
+                    vel[0][s] = Vs[ownV];
+                    vel[1][s] = Vs[FOV + ownV];
+                    vel[2][s] = Vs[2 * FOV + ownV];
                 }
                 if constexpr (kMomFromVel) {
 #pragma unroll
@@ -923,15 +934,15 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                        D1(Xw[0], Xw[1], Xw[3], Xw[4], k.a1[2], k.a2[2]);
         } else {
             const T* U = Vc;
-            const T* Vv = Vc + NPL;
+            const T* Vv = Vc + FOV;
             // nested differences unweighted, the two weights applied once:
             // D_x D_y v + D_z D_x w = a1x (a1y Du_x Du_y v + a1z Du_z Du_x w)
             auto dyv = [&](int mx) {
-                const int o = own + mx;
-                return D1u(Vv[o - 2 * LX], Vv[o - LX], Vv[o + LX], Vv[o + 2 * LX]);
+                const int o = ownV + mx;
+                return D1u(Vv[o - 2 * RSV], Vv[o - RSV], Vv[o + RSV], Vv[o + 2 * RSV]);
             };
             auto dxu = [&](int my) {
-                const int o = own + my * LX;
+                const int o = ownV + my * RSV;
                 return D1u(U[o - 2], U[o - 1], U[o + 1], U[o + 2]);
             };
             T dxdyv, dydxu;
