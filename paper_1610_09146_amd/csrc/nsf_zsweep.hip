@@ -443,13 +443,16 @@ struct PlaneLds {
 };
 
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
-// holds 2 * kPF * NPL and sV ring_slots * 3 * NPL values; in the fused form sH
-// holds 2 * kPF * NHALO values: the plane fields of the raw values each thread
-// loaded at its halo point for planes z+1, z+2 (a per-thread ring kept in LDS,
-// two slots since each thread reads plane z's before parking z+2's; so
-// every halo point is fetched once per plane, in the same iteration in
-// which the neighbouring tile fetches it as interior). Ends with a
-// barrier, so the caller may reuse the LDS for another tile right away.
+// holds 2 * kPF * NPL values (the plane fields of two planes), sV
+// ring_slots * 3 * NPL (the velocity ring). In the fused form sH holds
+// 2 * kPF * NHALO values: the plane fields of the raw values each thread
+// loaded at its halo point, parked until the point's plane is the centre
+// plane (a per-thread ring in LDS, so every halo point is fetched once per
+// plane, in the same iteration in which the neighbouring tile fetches it as
+// interior; two slots, since each thread reads plane z's entry before
+// parking plane z+2's in the same slot). With the D ring, sD holds
+// 3 * DSZ values. Ends with a barrier, so the caller may reuse the LDS for
+// another tile right away.
 template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
                                             T* __restrict__ sV, T* __restrict__ sH,
@@ -480,6 +483,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
     constexpr int RING = ring_slots<T, TY, FUSED, SS>();
     constexpr bool DR = d_ring<T, TY, SS>();
+    static_assert(!DR || G::DHALO <= G::NT, "the D-ring halo items need one thread each");
+    static_assert(RING == 5 || (RING == 4 && FUSED), "four ring slots rely on the fused loop order");
     // velocity gradients of the centre plane that earlier work already holds
     // unweighted: D_x w and D_y w in the z-cross queues (formed when the plane
     // led), D_x u and D_y v in the D ring; the x and y folds skip them
