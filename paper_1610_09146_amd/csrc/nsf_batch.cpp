@@ -4,8 +4,10 @@
 // step captured once in a hipGraph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <queue>
 #include <vector>
 
 #include "nsf.h"
@@ -25,7 +27,8 @@ struct nsf_batch {
     std::vector<double*> diag_partial;
     double* diag_out = nullptr;  // count * NSF_NDIAG doubles inside `work`
     void* desc_dev = nullptr;
-    int2* items_dev = nullptr;
+    int2* items_dev = nullptr;  // items in workgroup order
+    int* offs_dev = nullptr;     // workgroup b runs items [offs[b], offs[b+1])
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -59,11 +62,69 @@ int check_grids(int32_t count, const nsf_grid* grids, std::vector<Dims>& dims) {
     return NSF_OK;
 }
 
+// z-chunk of a batched instance: 48 planes from 64-point grids up (against
+// the single-grid 32 below 256 points: fewer chunk preambles, and on the
+// 64-instance mix of sizes 32 to 128 the batched step ran 1-2% faster than
+// with 32 or 64 planes).
+int batch_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 48 : d.nz); }
+
+// The pre-loop loads of a z-chunk (four planes of fields and halos) cost
+// about three planes of the loop.
+constexpr int kWarmPlanes = 3;
+
+// Static schedule of the persistent stage launch. The item list (instances
+// in order, each one's tiles in launch order) is cut into one contiguous band
+// of equal cost per XCD, so the tiles that share halos run under one L2; each
+// band is then dealt to its XCD's workgroups longest item first, each item to
+// the least-loaded workgroup (longest-processing-time rule; the stable sort
+// keeps equal items in tile order, so neighbouring tiles still run together).
+// Workgroup b runs on XCD b mod 8 as the (b / 8)-th of its XCD. Against a
+// round-robin deal of the list this raises the mean per-workgroup load from
+// 87-89% to 93% of the largest on the 64-instance mix of sizes 32 to 128.
+void schedule_items(const std::vector<int2>& items, const std::vector<int>& cost, int nblocks,
+                    std::vector<int2>& order, std::vector<int>& offs) {
+    const int per = nblocks / kXCD;
+    long long total = 0;
+    for (int c : cost) total += c;
+    std::vector<std::vector<int>> lists(nblocks);
+    size_t first = 0;
+    long long run = 0;
+    for (int x = 0; x < kXCD; ++x) {
+        // band x: items up to the cumulative cost total * (x + 1) / 8
+        size_t last = first;
+        const long long cut = total * (x + 1) / kXCD;
+        while (last < items.size() && (x == kXCD - 1 || run + cost[last] <= cut || last == first)) {
+            run += cost[last];
+            ++last;
+        }
+        std::vector<size_t> band;
+        for (size_t i = first; i < last; ++i) band.push_back(i);
+        std::stable_sort(band.begin(), band.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
+        using Load = std::pair<long long, int>;  // (load, index in the XCD)
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int j = 0; j < per; ++j) heap.push({0, j});
+        for (size_t i : band) {
+            Load l = heap.top();
+            heap.pop();
+            lists[(size_t)l.second * kXCD + x].push_back((int)i);
+            heap.push({l.first + cost[i], l.second});
+        }
+        first = last;
+    }
+    order.clear();
+    offs.assign(nblocks + 1, 0);
+    for (int b = 0; b < nblocks; ++b) {
+        for (int i : lists[b]) order.push_back(items[i]);
+        offs[b + 1] = (int)order.size();
+    }
+}
+
 template <typename T>
 int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* phys,
                  const double* dt, void* const* q, double* const* qacc, char* work) {
     std::vector<BatchDesc<T>> desc(b->count);
     std::vector<int2> items;
+    std::vector<int> cost;
     size_t off = 0;
     const size_t es = sizeof(T);
     for (int i = 0; i < b->count; ++i) {
@@ -81,21 +142,31 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
         bd.qacc = qacc[i];
         bd.dt = dt[i];
         int tx, ty, tz, zc;
-        tile_counts(d, default_zchunk(d), b->tile_y, &tx, &ty, &tz, &zc);
+        tile_counts(d, batch_zchunk(d), b->tile_y, &tx, &ty, &tz, &zc);
         bd.zchunk = zc;
         bd.tiles_x = tx;
         bd.tiles_y = ty;
         bd.tiles = tx * ty * tz;
-        for (int t = 0; t < bd.tiles; ++t) items.push_back(int2{i, t});
+        for (int t = 0; t < bd.tiles; ++t) {
+            items.push_back(int2{i, t});
+            const int z0 = (t / (tx * ty)) * zc;
+            cost.push_back(std::min(zc, d.nz - z0) + kWarmPlanes);
+        }
     }
     b->diag_out = (double*)(work + off);
     b->nitems = (int)items.size();
+    std::vector<int2> order;
+    std::vector<int> offs;
+    schedule_items(items, cost, b->nblocks, order, offs);
     hipError_t e = hipMalloc(&b->desc_dev, desc.size() * sizeof(BatchDesc<T>));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->items_dev, items.size() * sizeof(int2));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->items_dev, order.size() * sizeof(int2));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->offs_dev, offs.size() * sizeof(int));
     if (e == hipSuccess)
         e = hipMemcpy(b->desc_dev, desc.data(), desc.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(b->items_dev, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->items_dev, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->offs_dev, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
     return NSF_OK;
 }
@@ -103,8 +174,8 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
 template <typename T>
 void enqueue_step(nsf_batch* b, hipStream_t s) {
     for (int st = 0; st < 3; ++st)
-        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->nitems, st, b->nblocks,
-                           b->tile_y, s);
+        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->offs_dev, st,
+                           b->nblocks, b->tile_y, s);
 }
 
 void release(nsf_batch* b) {
@@ -113,6 +184,7 @@ void release(nsf_batch* b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->desc_dev) (void)hipFree(b->desc_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->offs_dev) (void)hipFree(b->offs_dev);
     delete b;
 }
 
@@ -172,10 +244,6 @@ int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys*
     b->q.assign(q, q + count);
     b->diag_partial.resize(count);
     b->tile_y = tile_y;
-    rc = precision == NSF_F64
-             ? build_tables<double>(b, dims, phys, dt, q, q_acc, (char*)work)
-             : build_tables<float>(b, dims, phys, dt, q, q_acc, (char*)work);
-    if (rc) { release(b); return rc; }
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -184,6 +252,10 @@ int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys*
     if (e != hipSuccess || cus < 1 || per_cu < 1) { release(b); return bfail(NSF_EHIP, "batch: occupancy query failed"); }
     b->nblocks = (cus * per_cu) / 8 * 8;  // a multiple of the XCD count
     if (b->nblocks < 8) b->nblocks = 8;
+    rc = precision == NSF_F64
+             ? build_tables<double>(b, dims, phys, dt, q, q_acc, (char*)work)
+             : build_tables<float>(b, dims, phys, dt, q, q_acc, (char*)work);
+    if (rc) { release(b); return rc; }
 
     // capture one step (three stage launches) into a graph on a private stream
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);

@@ -109,12 +109,14 @@ struct BatchDesc {
 
 // z-marching tiled residual kernels (nsf_zsweep.hip)
 // Tiles are 32 x tile_y (tile_y = 8 or 16) columns; zchunk planes deep.
+constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
 int default_zchunk(const Dims& d);
 int default_tile_y(int precision_bytes, const Dims& d);
 void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* tz, int* zc);
-// Persistent batched fused stage: items[i] = (instance, tile index).
+// Persistent batched fused stage: items[i] = (instance, tile index), in
+// workgroup order; workgroup b runs items[offs[b]] .. items[offs[b + 1] - 1].
 template <typename T>
-void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
                      int nblocks, int tile_y, hipStream_t s);
 template <typename T>
 int batch_blocks_per_cu(int tile_y);

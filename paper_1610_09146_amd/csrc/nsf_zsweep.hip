@@ -74,7 +74,6 @@ __device__ __forceinline__ void view_store(float x, __amdgpu_buffer_rsrc_t v, ui
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), v, off, 0, kPolicy);
 }
 
-constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
 constexpr int kTX = 32;  // tile width; the tile height is 8 or 16 rows
 
 __device__ __forceinline__ int pmod(int a, int n) {
@@ -1141,28 +1140,25 @@ k_ra_zsweep(ZArgs<T> A) {
     zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sD, sM);
 }
 
-// Persistent batched stage kernel: every workgroup walks the work list of
-// (instance, tile) items. Workgroup g (on XCD g mod 8) takes, in round r,
-// item r*G + (g mod 8)*(G/8) + g/8, so each XCD sweeps a contiguous band of
-// tiles per round. Stage s reads state s of the rotation q -> qb -> qc -> q.
+// Persistent batched stage kernel: workgroup b runs its own run of the
+// (instance, tile) items, items[offs[b]] .. items[offs[b + 1] - 1], from a
+// schedule built on the host (one band of neighbouring tiles per XCD, evened
+// out by item cost). Stage s reads state s of the rotation q -> qb -> qc -> q.
 template <typename T, int TX, int TY>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
-k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items, int nitems,
-           int stage) {
+k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items,
+           const int* __restrict__ offs, int stage) {
     using G = Geom<TX, TY>;
     __shared__ T sP[2 * kPF * G::NPL];
     __shared__ T sV[ring_slots<T, TY, true, false>() * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, true>() ? 2 * kPF * G::NHALO : 1];
     __shared__ T sD[d_ring<T, TY, false>() ? 3 * G::DSZ : 1];
-    const int nb = gridDim.x;
-    const int slot = (blockIdx.x % kXCD) * (nb / kXCD) + blockIdx.x / kXCD;
+    const int first = offs[blockIdx.x], last = offs[blockIdx.x + 1];
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
     const double B_[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
-    for (int base = 0; base < nitems; base += nb) {
-        const int item = base + slot;
-        if (item >= nitems) break;
-        const int2 it = items[item];
+    for (int i = first; i < last; ++i) {
+        const int2 it = items[i];
         const BatchDesc<T>& bd = desc[it.x];
         ZArgs<T> A;
         A.d = bd.d;
@@ -1245,15 +1241,15 @@ void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
 }
 
 template <typename T>
-void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, int nitems, int stage,
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
                      int nblocks, int tile_y, hipStream_t s) {
     TimerScope ts("ra_batch", s);
     if (tile_y == 16)
         hipLaunchKernelGGL((k_ra_batch<T, kTX, 16>), dim3(nblocks), dim3(kTX * 16), 0, s, desc,
-                           items, nitems, stage);
+                           items, offs, stage);
     else
         hipLaunchKernelGGL((k_ra_batch<T, kTX, 8>), dim3(nblocks), dim3(kTX * 8), 0, s, desc, items,
-                           nitems, stage);
+                           offs, stage);
 }
 
 template <typename T>
@@ -1300,7 +1296,7 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
 }
 
 #define NSF_INST(T)                                                                          \
-    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, int, int, int, int,   \
+    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, const int*, int, int, int, \
                                      hipStream_t);                                            \
     template int batch_blocks_per_cu<T>(int);                                                 \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
