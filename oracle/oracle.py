@@ -181,6 +181,34 @@ def rk_step(q: np.ndarray, phys, dt: float, nsteps: int = 1, prec: str = "d") ->
     return q
 
 
+def rk_step_slab(q_slab: np.ndarray, nz_glob: int, phys, dt: float, prec: str = "d") -> np.ndarray:
+    """One step of the same low-storage RK3 (2R form, Section 2) on a z-slab.
+
+    q_slab holds planes k0-6 .. k1+5 of a periodic nz_glob-plane state (full
+    x and y extents). A stage's residual on a plane needs the two planes on
+    either side, so each of the three stages gives up two planes at both
+    ends; the result, planes k0 .. k1-1 after the step, equals what the
+    full-grid step gives there. The update is the one of oracle_rk_step:
+    q <- q_acc + a_s dt r (first two stages), then q_acc <- q_acc + b_s dt r,
+    the step's result being q_acc.
+    """
+    t = _dtype(prec)
+    q = np.ascontiguousarray(q_slab, dtype=t)
+    if q.shape[1] < 13:
+        raise ValueError("slab needs at least 13 planes (one output plane)")
+    a = (t(2) / t(3), t(5) / t(12))
+    b = (t(1) / t(4), t(3) / t(20), t(3) / t(5))
+    tdt = t(dt)
+    acc = q
+    for s in range(3):
+        r = rhs_slab(q, nz_glob, phys, prec=prec)  # interior planes of this slab
+        acc = acc[:, 2:-2]
+        if s < 2:
+            q = np.ascontiguousarray(acc + a[s] * tdt * r)
+        acc = acc + b[s] * tdt * r
+    return acc
+
+
 def diagnostics(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
     q = np.ascontiguousarray(q, dtype=_dtype(prec))
     nx, ny, nz = _shape_of(q)

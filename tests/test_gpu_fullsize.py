@@ -1,0 +1,62 @@
+"""GPU: the timed workload at full size, in the launch configuration the
+benchmark times: 512^3 Taylor-Green (pointwise +-1e-3 perturbation, seed
+1610, dt = 4.23125e-4), one monitored RK step of the fused RA form with
+32 x 16 tiles and 64-plane z-chunks (Section 2 time loop, Section 3 set-up).
+
+The oracle cannot advance 2^27 points in seconds, but a step's result on a
+few z-planes depends only on six planes either side of them, so sampled
+planes (at the periodic seam and in the interior) are checked against the
+oracle's slab step in x87 extended precision. The state moves by about 1e-3
+of its size in one step, so the error is measured on the increment
+q(t + dt) - q(t), against max(1e-12, 4 F) with F the oracle's own
+double-precision error on the same slab.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1610_09146_amd import workloads as W
+from tests.helpers import rel_err
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1610_09146_amd import nsf  # noqa: E402
+
+PHYS = W.TGV_PHYS
+N = 512
+TUNE = {"fuse": 1, "block_y": 16, "zchunk": 64}
+# output planes [k0, k1): the seam at z = 0, the middle, the seam at z = N
+SAMPLES = [(0, 2), (N // 2 - 1, N // 2 + 1), (N - 2, N)]
+
+
+def _planes(t, k0, k1):
+    return t[:, [(k % N) for k in range(k0, k1)]].cpu().numpy()
+
+
+def test_512_monitored_fused_step_sampled_planes():
+    print(f"case fullsize fused monitored step {N} {TUNE}", flush=True)
+    s = nsf.Solver((N, N, N), PHYS, "RA", "f64", tune=TUNE)
+    s.init(W.tgv_pointwise(1610))
+    dt = W.tgv_dt(N)
+    slabs = {k0: _planes(s.q, k0 - 6, k1 + 6) for k0, k1 in SAMPLES}
+    mon = torch.zeros(4, dtype=torch.float64, device="cuda")
+    s.step_monitored(dt, 1, mon)
+    torch.cuda.synchronize()
+    for k0, k1 in SAMPLES:
+        q0 = slabs[k0]
+        base = q0[:, 6:-6]
+        got = _planes(s.q, k0, k1)
+        ref = O.rk_step_slab(q0.astype(np.longdouble), N, PHYS, dt, prec="ld")
+        dbl = O.rk_step_slab(q0, N, PHYS, dt, prec="d")
+        ref_inc = (ref - base).astype(np.float64)
+        err = rel_err(got - base, ref_inc)
+        floor = rel_err(dbl - base, ref_inc)
+        assert np.all(err <= np.maximum(1e-12, 4 * floor)), (k0, err, floor)
+    # the accumulator equals the state at a step boundary
+    assert torch.equal(s.q, s.q_acc)
+    del s
+    torch.cuda.empty_cache()

@@ -382,6 +382,24 @@ def test_slab_entry_points_match_full_grid():
         assert np.array_equal(rs, r[:, idx[2:4]])
 
 
+
+@pytest.mark.parametrize("prec", ["d", "ld"])
+def test_slab_rk_step_matches_full_grid(prec):
+    # the full-size check of the timed RK step advances slabs cut from the
+    # grid: one slab step must give the full-grid step on its output planes
+    shape = (12, 10, 20)
+    tgv = {"pert_kind": 1, "pert_amp": 0.05, "seed": 22}
+    q = O.init(shape, PHYS, tgv, prec=prec)
+    dt = 0.01
+    full = O.rk_step(q, PHYS, dt, 1, prec=prec)
+    for k0, m in ((0, 2), (9, 3), (18, 2)):
+        idx = [(k % 20) for k in range(k0 - 6, k0 + m + 6)]
+        got = O.rk_step_slab(q[:, idx], 20, PHYS, dt, prec=prec)
+        assert got.shape == (5, m, 10, 12)
+        assert np.array_equal(got, full[:, idx[6:6 + m]])
+    with pytest.raises(ValueError):
+        O.rk_step_slab(q[:, :12], 20, PHYS, dt, prec=prec)
+
 # ------------------------------------------------------------ two dimensions
 # nz = 1: the z-independent problem (the paper counts its arrays for 2D as
 # well as 3D, Section 2). The Taylor-Green initial state is its z = 0 plane,
