@@ -181,7 +181,8 @@ def rk_step(q: np.ndarray, phys, dt: float, nsteps: int = 1, prec: str = "d") ->
     return q
 
 
-def rk_step_slab(q_slab: np.ndarray, nz_glob: int, phys, dt: float, prec: str = "d") -> np.ndarray:
+def rk_step_slab(q_slab: np.ndarray, nz_glob: int, phys, dt: float, prec: str = "d",
+                 stage_dtype=None) -> np.ndarray:
     """One step of the same low-storage RK3 (2R form, Section 2) on a z-slab.
 
     q_slab holds planes k0-6 .. k1+5 of a periodic nz_glob-plane state (full
@@ -191,6 +192,10 @@ def rk_step_slab(q_slab: np.ndarray, nz_glob: int, phys, dt: float, prec: str = 
     full-grid step gives there. The update is the one of oracle_rk_step:
     q <- q_acc + a_s dt r (first two stages), then q_acc <- q_acc + b_s dt r,
     the step's result being q_acc.
+
+    stage_dtype (e.g. numpy.float32) models the single-precision form: the
+    state each stage's residual is evaluated on is first rounded through
+    that type, while the accumulator stays in ``prec``.
     """
     t = _dtype(prec)
     q = np.ascontiguousarray(q_slab, dtype=t)
@@ -201,6 +206,8 @@ def rk_step_slab(q_slab: np.ndarray, nz_glob: int, phys, dt: float, prec: str = 
     tdt = t(dt)
     acc = q
     for s in range(3):
+        if stage_dtype is not None:
+            q = q.astype(stage_dtype).astype(t)
         r = rhs_slab(q, nz_glob, phys, prec=prec)  # interior planes of this slab
         acc = acc[:, 2:-2]
         if s < 2:

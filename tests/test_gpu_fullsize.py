@@ -1,7 +1,8 @@
-"""GPU: the timed workload at full size, in the launch configuration the
+"""GPU: the timed workloads at full size, in the launch configurations the
 benchmark times: 512^3 Taylor-Green (pointwise +-1e-3 perturbation, seed
-1610, dt = 4.23125e-4), one monitored RK step of the fused RA form with
-32 x 16 tiles and 64-plane z-chunks (Section 2 time loop, Section 3 set-up).
+1610, dt = 4.23125e-4), one monitored RK step of the fused RA form, in
+double precision with 32 x 16 tiles and in the single-precision form with
+32 x 8 tiles, 64-plane z-chunks (Section 2 time loop, Section 3 set-up).
 
 The oracle cannot advance 2^27 points in seconds, but a step's result on a
 few z-planes depends only on six planes either side of them, so sampled
@@ -9,7 +10,10 @@ planes (at the periodic seam and in the interior) are checked against the
 oracle's slab step in x87 extended precision. The state moves by about 1e-3
 of its size in one step, so the error is measured on the increment
 q(t + dt) - q(t), against max(1e-12, 4 F) with F the oracle's own
-double-precision error on the same slab.
+double-precision error on the same slab. The single-precision form is
+checked on its FP64 accumulator against the oracle step whose stage states
+are rounded to FP32 (as the form's fields are), at 4 times the effect of
+that rounding.
 """
 import numpy as np
 import pytest
@@ -58,5 +62,31 @@ def test_512_monitored_fused_step_sampled_planes():
         assert np.all(err <= np.maximum(1e-12, 4 * floor)), (k0, err, floor)
     # the accumulator equals the state at a step boundary
     assert torch.equal(s.q, s.q_acc)
+    del s
+    torch.cuda.empty_cache()
+
+
+def test_512_monitored_fused_step_f32_form_sampled_planes():
+    tune = {"fuse": 1, "block_y": 8, "zchunk": 64}
+    print(f"case fullsize fused monitored step f32 {N} {tune}", flush=True)
+    s = nsf.Solver((N, N, N), PHYS, "RA", "f32", tune=tune)
+    s.init(W.tgv_pointwise(1610))
+    dt = W.tgv_dt(N)
+    slabs = {k0: _planes(s.q_acc, k0 - 6, k1 + 6) for k0, k1 in SAMPLES}
+    for k0, k1 in SAMPLES:  # the fields are the accumulator rounded to FP32
+        assert np.array_equal(_planes(s.q, k0, k1), slabs[k0][:, 6:-6].astype(np.float32))
+    mon = torch.zeros(4, dtype=torch.float64, device="cuda")
+    s.step_monitored(dt, 1, mon)
+    torch.cuda.synchronize()
+    for k0, k1 in SAMPLES:
+        q0 = slabs[k0].astype(np.longdouble)
+        base = slabs[k0][:, 6:-6]
+        got = _planes(s.q_acc, k0, k1)
+        ref = O.rk_step_slab(q0, N, PHYS, dt, prec="ld", stage_dtype=np.float32)
+        unrounded = O.rk_step_slab(q0, N, PHYS, dt, prec="ld")
+        ref_inc = (ref - base).astype(np.float64)
+        err = rel_err(got - base, ref_inc)
+        bar = 4 * rel_err((unrounded - base).astype(np.float64), ref_inc)
+        assert np.all(err <= bar), (k0, err, bar)
     del s
     torch.cuda.empty_cache()

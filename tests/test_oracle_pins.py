@@ -399,6 +399,20 @@ def test_slab_rk_step_matches_full_grid(prec):
         assert np.array_equal(got, full[:, idx[6:6 + m]])
     with pytest.raises(ValueError):
         O.rk_step_slab(q[:, :12], 20, PHYS, dt, prec=prec)
+    # the single-precision model: rounding through float64 changes nothing in
+    # double precision; through float32 it moves the step's increment by
+    # single-precision rounding (relative 1e-8 .. 1e-4), no more
+    idx = [(k % 20) for k in range(-6, 8)]
+    plain = O.rk_step_slab(q[:, idx], 20, PHYS, dt, prec=prec)
+    if prec == "d":
+        assert np.array_equal(O.rk_step_slab(q[:, idx], 20, PHYS, dt, prec=prec,
+                                             stage_dtype=np.float64), plain)
+    r32 = O.rk_step_slab(q[:, idx], 20, PHYS, dt, prec=prec, stage_dtype=np.float32)
+    base = q[:, idx[6:8]]
+    inc = (plain - base).astype(np.float64).reshape(5, -1)
+    d32 = (r32 - plain).astype(np.float64).reshape(5, -1)
+    rel = np.abs(d32).max(axis=1) / np.abs(inc).max(axis=1)
+    assert np.all(rel > 1e-9) and np.all(rel < 1e-4), rel
 
 # ------------------------------------------------------------ two dimensions
 # nz = 1: the z-independent problem (the paper counts its arrays for 2D as
