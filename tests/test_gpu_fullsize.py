@@ -2,7 +2,9 @@
 benchmark times: 512^3 Taylor-Green (pointwise +-1e-3 perturbation, seed
 1610, dt = 4.23125e-4), one monitored RK step of the fused RA form, in
 double precision with 32 x 16 tiles and in the single-precision form with
-32 x 8 tiles, 64-plane z-chunks (Section 2 time loop, Section 3 set-up).
+32 x 8 tiles, 64-plane z-chunks (Section 2 time loop, Section 3 set-up);
+and at 256^3 (dt = 8.4625e-4) the monitored step of each algorithm the
+benchmark compares there (BL, SS, RA with stored primitives).
 
 The oracle cannot advance 2^27 points in seconds, but a step's result on a
 few z-planes depends only on six planes either side of them, so sampled
@@ -88,5 +90,37 @@ def test_512_monitored_fused_step_f32_form_sampled_planes():
         err = rel_err(got - base, ref_inc)
         bar = 4 * rel_err((unrounded - base).astype(np.float64), ref_inc)
         assert np.all(err <= bar), (k0, err, bar)
+    del s
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("variant", ["BL", "SS", "RA"])
+def test_256_monitored_step_sampled_planes(variant):
+    # the 256^3 comparison of the algorithms (pointwise +-1e-3, seed 1610,
+    # dt = 8.4625e-4): each variant's monitored step at its default tuning
+    n = 256
+    print(f"case fullsize monitored step {variant} {n}", flush=True)
+    s = nsf.Solver((n, n, n), PHYS, variant, "f64")
+    s.init(W.tgv_pointwise(1610))
+    dt = W.tgv_dt(n)
+    samples = [(0, 2), (n // 2 - 1, n // 2 + 1), (n - 2, n)]
+
+    def planes(t, k0, k1):
+        return t[:, [(k % n) for k in range(k0, k1)]].cpu().numpy()
+
+    slabs = {k0: planes(s.q, k0 - 6, k1 + 6) for k0, k1 in samples}
+    mon = torch.zeros(4, dtype=torch.float64, device="cuda")
+    s.step_monitored(dt, 1, mon)
+    torch.cuda.synchronize()
+    for k0, k1 in samples:
+        q0 = slabs[k0]
+        base = q0[:, 6:-6]
+        got = planes(s.q, k0, k1)
+        ref = O.rk_step_slab(q0.astype(np.longdouble), n, PHYS, dt, prec="ld")
+        dbl = O.rk_step_slab(q0, n, PHYS, dt, prec="d")
+        ref_inc = (ref - base).astype(np.float64)
+        err = rel_err(got - base, ref_inc)
+        floor = rel_err(dbl - base, ref_inc)
+        assert np.all(err <= np.maximum(1e-12, 4 * floor)), (k0, err, floor)
     del s
     torch.cuda.empty_cache()
