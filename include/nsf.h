@@ -220,14 +220,15 @@ int nsf_tune_get(const nsf_grid *g, int precision, nsf_tune_result *out);
 /* ---------------------------------------------------------------- batched form
  * Many independent Taylor-Green-type instances (own grid, parameters, dt)
  * advance together with the fused recompute-all stage: one persistent
- * launch per RK stage walks a work list of (instance, tile) items across all
- * instances, and the three stage launches of a step are captured once in a
- * hipGraph. Each instance's q (precision dtype) and q_acc (double) are
+ * launch per RK stage in which every workgroup runs its own run of
+ * (instance, tile) items, taken from a schedule built once on the host (one
+ * band of neighbouring tiles of equal cost per XCD, dealt longest first),
+ * and the three stage launches of a step are captured once in a hipGraph. Each instance's q (precision dtype) and q_acc (double) are
  * caller-owned device buffers with the single-grid contract of nsf_rk_step;
  * `work` (nsf_batch_workspace_bytes) holds the other two stage states and
  * the diagnostics scratch of every instance and must stay allocated until
  * nsf_batch_destroy. The handle owns only the graph, a private capture
- * stream and the small device work list it allocates. */
+ * stream and the small device work list and schedule it allocates. */
 typedef struct nsf_batch nsf_batch;
 
 int nsf_batch_workspace_bytes(int32_t count, const nsf_grid *grids, int precision, size_t *bytes);
