@@ -15,30 +15,53 @@ namespace nsf {
 
 namespace {
 
-constexpr int kBX = 64, kBY = 4;
+constexpr int kBX = 64, kBY = 4, kBZ = 4;
 
-// One derivative loop: out = D_AX f (ORDER 1) or D2_AX f (ORDER 2).
+// One derivative loop: out = D_AX f (ORDER 1) or D2_AX f (ORDER 2). A block
+// covers kBX x kBY points of kBZ consecutive planes (a quarter of the
+// workgroups of a one-plane block: the 512^3 derivative loops ran 10%
+// faster; 2 to 32 planes measured alike); along z (AX = 2) each thread
+// slides a five-plane window down its column, one new load per plane.
 template <typename T, int AX, int ORDER>
 __global__ void __launch_bounds__(kBX * kBY) k_bl_deriv(Dims d, Coef<T> c, const T* __restrict__ f,
                                                         T* __restrict__ out) {
     const int i = blockIdx.x * kBX + threadIdx.x;
     const int j = blockIdx.y * kBY + threadIdx.y;
-    const int k = blockIdx.z;
+    const int k0 = blockIdx.z * kBZ;
+    const int k1 = min(k0 + kBZ, d.nz);
     if (i >= d.nx || j >= d.ny) return;
-    const size_t sx = 1, sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
-    const size_t base = (size_t)k * sz + (size_t)j * sy;
-    T v[5];
+    const size_t sy = (size_t)d.nx, sz = (size_t)d.nx * d.ny;
+    const size_t col = (size_t)j * sy + i;
+    auto emit = [&](const T v[5], int k) {
+        if (ORDER == 1) out[(size_t)k * sz + col] = d1(v[0], v[1], v[3], v[4], c.a1[AX], c.a2[AX]);
+        else out[(size_t)k * sz + col] = d2(v[0], v[1], v[2], v[3], v[4], c.b0[AX], c.b1[AX], c.b2[AX]);
+    };
+    if (AX == 2) {
+        T v[5];
 #pragma unroll
-    for (int m = -2; m <= 2; ++m) {
-        size_t idx;
-        if (AX == 0) idx = base + wrap(i + m, d.nx) * sx;
-        else if (AX == 1) idx = (size_t)k * sz + (size_t)wrap(j + m, d.ny) * sy + i;
-        else idx = (size_t)wrap(k + m, d.nz) * sz + (size_t)j * sy + i;
-        v[m + 2] = (ORDER == 2 || m != 0) ? f[idx] : T(0);
+        for (int m = -2; m <= 1; ++m) v[m + 2] = f[(size_t)wrap(k0 + m, d.nz) * sz + col];
+        T nxt = f[(size_t)wrap(k0 + 2, d.nz) * sz + col];
+        for (int k = k0; k < k1; ++k) {
+            v[4] = nxt;
+            if (k + 1 < k1) nxt = f[(size_t)wrap(k + 3, d.nz) * sz + col];
+            emit(v, k);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[m] = v[m + 1];
+        }
+    } else {
+#pragma unroll 4
+        for (int k = k0; k < k1; ++k) {
+            const size_t base = (size_t)k * sz;
+            T v[5];
+#pragma unroll
+            for (int m = -2; m <= 2; ++m) {
+                const size_t idx = AX == 0 ? base + (size_t)j * sy + wrap(i + m, d.nx)
+                                           : base + (size_t)wrap(j + m, d.ny) * sy + i;
+                v[m + 2] = (ORDER == 2 || m != 0) ? f[idx] : T(0);
+            }
+            emit(v, k);
+        }
     }
-    const size_t o = base + i;
-    if (ORDER == 1) out[o] = d1(v[0], v[1], v[3], v[4], c.a1[AX], c.a2[AX]);
-    else out[o] = d2(v[0], v[1], v[2], v[3], v[4], c.b0[AX], c.b1[AX], c.b2[AX]);
 }
 
 // Residual loop of BL: every derivative read from its work array.
@@ -86,7 +109,8 @@ __global__ void __launch_bounds__(256) k_bl_assemble(Dims d, Coef<T> c, const T*
 
 template <typename T, int AX, int ORDER>
 void launch_one(const Dims& d, const Coef<T>& c, const T* f, T* out, hipStream_t s) {
-    const dim3 g((unsigned)((d.nx + kBX - 1) / kBX), (unsigned)((d.ny + kBY - 1) / kBY), (unsigned)d.nz);
+    const dim3 g((unsigned)((d.nx + kBX - 1) / kBX), (unsigned)((d.ny + kBY - 1) / kBY),
+                 (unsigned)((d.nz + kBZ - 1) / kBZ));
     hipLaunchKernelGGL((k_bl_deriv<T, AX, ORDER>), g, dim3(kBX, kBY), 0, s, d, c, f, out);
 }
 
