@@ -8,6 +8,15 @@ namespace {
 
 constexpr int kBlock = 256;
 
+// Streaming access (non-temporal hint) for the arrays the primitive and
+// stage-update loops read or write once per pass: at 512^3 those loops ran
+// 5-9% faster with it (the BL product loop, whose output is re-read right
+// away by the next derivative loop, ran 5% slower and keeps plain access).
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) { return __builtin_nontemporal_load(p); }
+template <typename V>
+__device__ __forceinline__ void st_nt(V v, V* p) { __builtin_nontemporal_store(v, p); }
+
 inline unsigned grid_for(size_t n, int per_block) {
     size_t b = (n + per_block - 1) / per_block;
     return (unsigned)(b < 1 ? 1 : b);
@@ -71,12 +80,13 @@ __global__ void __launch_bounds__(kBlock) k_prims(Dims d, Coef<T> c, const T* __
     const size_t idx = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (idx >= d.npts) return;
     const size_t n = d.npts;
-    Prim<T> P = primitives(q[idx], q[n + idx], q[2 * n + idx], q[3 * n + idx], q[4 * n + idx], c);
-    prim[idx] = P.u;
-    prim[n + idx] = P.v;
-    prim[2 * n + idx] = P.w;
-    prim[3 * n + idx] = P.p;
-    prim[4 * n + idx] = P.t;
+    Prim<T> P = primitives(ld_nt(q + idx), ld_nt(q + n + idx), ld_nt(q + 2 * n + idx),
+                           ld_nt(q + 3 * n + idx), ld_nt(q + 4 * n + idx), c);
+    st_nt(P.u, prim + idx);
+    st_nt(P.v, prim + n + idx);
+    st_nt(P.w, prim + 2 * n + idx);
+    st_nt(P.p, prim + 3 * n + idx);
+    st_nt(P.t, prim + 4 * n + idx);
 }
 
 // BL primitives in three loops (Section 2, BL paragraph): no loop both
@@ -122,11 +132,11 @@ __global__ void __launch_bounds__(kBlock) k_update(size_t n5, StageCoef sc, cons
                                                    T* __restrict__ q, double* __restrict__ qacc) {
     const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= n5) return;
-    const double rr = (double)r[e];
-    const double a = qacc[e];
+    const double rr = (double)ld_nt(r + e);
+    const double a = ld_nt(qacc + e);
     const double na = fma(sc.b_dt, rr, a);
-    qacc[e] = na;
-    q[e] = sc.last ? (T)na : (T)fma(sc.a_dt, rr, a);
+    st_nt(na, qacc + e);
+    st_nt(sc.last ? (T)na : (T)fma(sc.a_dt, rr, a), q + e);
 }
 
 // BL product ("function") loop: out = f * g into the reused work array.
