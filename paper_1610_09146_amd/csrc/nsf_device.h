@@ -42,6 +42,14 @@ struct Coef {
     T b0s;         // b0[0] + b0[1] + b0[2]: centre weight of the Laplacian
 };
 
+// Streaming (non-temporal) access for grid arrays a loop reads or writes
+// once: the arrays are far larger than any cache, and keeping them out of L2
+// leaves it to the data that is re-read (stencil neighbours).
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) { return __builtin_nontemporal_load(p); }
+template <typename V>
+__device__ __forceinline__ void st_nt(V v, V* p) { __builtin_nontemporal_store(v, p); }
+
 // periodic index for offsets |i - [0, n)| <= 2: one period when n >= 3, a
 // full modulo for the single-plane (two-dimensional) axis
 __device__ __forceinline__ int wrap(int i, int n) {

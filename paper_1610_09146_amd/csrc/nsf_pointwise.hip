@@ -8,14 +8,10 @@ namespace {
 
 constexpr int kBlock = 256;
 
-// Streaming access (non-temporal hint) for the arrays the primitive and
-// stage-update loops read or write once per pass: at 512^3 those loops ran
-// 5-9% faster with it (the BL product loop, whose output is re-read right
-// away by the next derivative loop, ran 5% slower and keeps plain access).
-template <typename V>
-__device__ __forceinline__ V ld_nt(const V* p) { return __builtin_nontemporal_load(p); }
-template <typename V>
-__device__ __forceinline__ void st_nt(V v, V* p) { __builtin_nontemporal_store(v, p); }
+// The primitive and stage-update loops stream their arrays (ld_nt / st_nt):
+// at 512^3 they ran 5-9% faster so. The BL product loop, whose output the
+// next derivative loop re-reads at once, ran 5% slower so and keeps plain
+// access.
 
 inline unsigned grid_for(size_t n, int per_block) {
     size_t b = (n + per_block - 1) / per_block;
