@@ -18,11 +18,13 @@ namespace {
 constexpr int kBX = 64, kBY = 4, kBZ = 4, kRY = 4;
 
 // One derivative loop: out = D_AX f (ORDER 1) or D2_AX f (ORDER 2). Along
-// x a block covers kBX x kBY points of kBZ consecutive planes (a quarter of
-// the workgroups of a one-plane block: 10% faster at 512^3; 2 to 32 planes
-// measured alike). Along y and z each thread slides a five-point window
-// down its column, one new load per point: over kRY rows of one plane (y;
-// 11% faster than the x form) or over kBZ planes (z).
+// x a block covers a row segment of kBX * kBY points in kBZ consecutive
+// planes (four planes per block: 10% faster at 512^3 than one, 2 to 32
+// measured alike; the long segment has fewer ends, whose halo reads fetch
+// partly used lines: 2% more). Along y and z each thread slides a
+// five-point window down its column, one new load per point: over kRY rows
+// of one plane (y; 11% faster than the x form) or over kBZ planes (z), as a
+// column of kBX x kBY points.
 template <typename T, int AX, int ORDER>
 __global__ void __launch_bounds__(kBX * kBY) k_bl_deriv(Dims d, Coef<T> c, const T* __restrict__ f,
                                                         T* __restrict__ out) {
@@ -53,8 +55,9 @@ __global__ void __launch_bounds__(kBX * kBY) k_bl_deriv(Dims d, Coef<T> c, const
         }
         return;
     }
-    const int i = blockIdx.x * kBX + threadIdx.x;
-    const int j = blockIdx.y * kBY + threadIdx.y;
+    const int i = AX == 0 ? (blockIdx.x * kBY + threadIdx.y) * kBX + threadIdx.x
+                          : blockIdx.x * kBX + threadIdx.x;
+    const int j = AX == 0 ? blockIdx.y : blockIdx.y * kBY + threadIdx.y;
     const int k0 = blockIdx.z * kBZ;
     const int k1 = min(k0 + kBZ, d.nz);
     if (i >= d.nx || j >= d.ny) return;
@@ -142,8 +145,9 @@ __global__ void __launch_bounds__(256) k_bl_assemble(Dims d, Coef<T> c, const T*
 
 template <typename T, int AX, int ORDER>
 void launch_one(const Dims& d, const Coef<T>& c, const T* f, T* out, hipStream_t s) {
-    const dim3 g((unsigned)((d.nx + kBX - 1) / kBX),
-                 AX == 1 ? (unsigned)((d.ny + kBY * kRY - 1) / (kBY * kRY)) : (unsigned)((d.ny + kBY - 1) / kBY),
+    const dim3 g(AX == 0 ? (unsigned)((d.nx + kBX * kBY - 1) / (kBX * kBY)) : (unsigned)((d.nx + kBX - 1) / kBX),
+                 AX == 1 ? (unsigned)((d.ny + kBY * kRY - 1) / (kBY * kRY))
+                         : AX == 0 ? (unsigned)d.ny : (unsigned)((d.ny + kBY - 1) / kBY),
                  AX == 1 ? (unsigned)d.nz : (unsigned)((d.nz + kBZ - 1) / kBZ));
     hipLaunchKernelGGL((k_bl_deriv<T, AX, ORDER>), g, dim3(kBX, kBY), 0, s, d, c, f, out);
 }
