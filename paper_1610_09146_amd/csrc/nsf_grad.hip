@@ -76,20 +76,38 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
         hidx = hy * kLX + hx;
         hcol = (size_t)pmodg(y0 + hy - 2, d.ny) * d.nx + pmodg(x0 + hx - 2, d.nx);
     }
-    auto enter = [&](int zz) {
+    // the velocity of plane zz at this thread's point and halo point,
+    // fetched one plane ahead of use so the load latency overlaps a plane's
+    // work
+    struct Raw {
+        T own[3], halo[3];
+    };
+    auto fetch = [&](int zz) {
+        Raw r;
         const size_t po = (size_t)pmodg(zz, d.nz) * plane;
-        T* V = sV + pmodg(zz, kRing) * 3 * kNPL;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) V[a * kNPL + own] = prim[a * n + po + col];
+        for (int a = 0; a < 3; ++a) r.own[a] = prim[a * n + po + col];
         if (hval)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) V[a * kNPL + hidx] = prim[a * n + po + hcol];
+            for (int a = 0; a < 3; ++a) r.halo[a] = prim[a * n + po + hcol];
+        return r;
     };
-    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s);
+    auto enter = [&](int zz, const Raw& r) {
+        T* V = sV + pmodg(zz, kRing) * 3 * kNPL;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) V[a * kNPL + own] = r.own[a];
+        if (hval)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) V[a * kNPL + hidx] = r.halo[a];
+    };
+    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s));
+    Raw nxt = fetch(z0 + 2);
     const T a1x = A.c.a1[0], a2x = A.c.a2[0], a1y = A.c.a1[1], a2y = A.c.a2[1];
     const T a1z = A.c.a1[2], a2z = A.c.a2[2];
     for (int z = z0; z < z1; ++z) {
-        enter(z + 2);
+        const Raw cur = nxt;
+        if (z + 1 < z1) nxt = fetch(z + 3);
+        enter(z + 2, cur);
         __syncthreads();
         if (active) {
             const size_t o = (size_t)z * plane + col;
