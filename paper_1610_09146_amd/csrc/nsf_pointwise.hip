@@ -136,12 +136,16 @@ __global__ void __launch_bounds__(kBlock) k_update(size_t n5, StageCoef sc, cons
 }
 
 // BL product ("function") loop: out = f * g into the reused work array.
+// Four elements per thread, a block-width apart (9% faster than one at
+// 512^3; the primitive and update loops ran 7-12% slower so and keep one).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_product(size_t n, const T* __restrict__ f,
                                                     const T* __restrict__ g, T* __restrict__ out) {
-    const size_t e = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= n) return;
-    out[e] = f[e] * g[e];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const size_t e = (size_t)blockIdx.x * (4 * kBlock) + r * kBlock + threadIdx.x;
+        if (e < n) out[e] = f[e] * g[e];
+    }
 }
 
 // Streaming copy, one 16-byte element per lane with non-temporal hints
@@ -194,7 +198,7 @@ void launch_update(const Dims& d, const StageCoef& sc, const T* r, T* q, double*
 template <typename T>
 void launch_product(const Dims& d, const T* f, const T* g, T* out, hipStream_t s) {
     TimerScope ts("bl_product", s);
-    hipLaunchKernelGGL(k_product<T>, dim3(grid_for(d.npts, kBlock)), dim3(kBlock), 0, s, d.npts, f, g, out);
+    hipLaunchKernelGGL(k_product<T>, dim3(grid_for(d.npts, 4 * kBlock)), dim3(kBlock), 0, s, d.npts, f, g, out);
 }
 
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
