@@ -349,7 +349,7 @@ def main() -> int:
                     help="first run a plain 1 GiB device copy three times (counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(the domain-decomposed form is a design note only); run with --gpus 1",
               file=sys.stderr)
         return 2

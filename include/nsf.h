@@ -51,7 +51,7 @@ typedef enum {
     NSF_EINVAL = -1,       /* bad argument, size or pointer            */
     NSF_EWORKSPACE = -2,   /* work buffer smaller than required        */
     NSF_EHIP = -3,         /* HIP runtime or launch error              */
-    NSF_EUNSUPPORTED = -4, /* combination not provided by this build   */
+    NSF_EUNSUPPORTED = -4, /* combination the library does not provide */
     NSF_ENONFINITE = -5    /* diagnostics found NaN/Inf in the state   */
 } nsf_status;
 
