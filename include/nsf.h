@@ -8,8 +8,9 @@
  * What the library computes (paper Section 2):
  *   - the residual R(q) of the 3D compressible Navier-Stokes equations with
  *     constant viscosity, eqs (1)-(3), stress eq (4), heat flux eq (5),
- *     pressure and temperature eqs (6)-(9); convective terms in the
- *     skew-symmetric form eq (10); viscous terms expanded to second
+ *     pressure and temperature eqs (6)-(7), or (9)-(10) from the
+ *     conservative variables; convective terms in the skew-symmetric
+ *     form eq (8); viscous terms expanded to second
  *     derivatives; fourth-order central differences on a periodic grid;
  *   - the three-stage low-storage Runge-Kutta time advance (Figure 1);
  *   - in the paper's derivative-storage algorithms BL, RA, SN, RS, SS
@@ -60,7 +61,7 @@ typedef enum {
  *           array; products staged in one reused work array; primitives in
  *           three separate loops (u_i, then p by eq (6), then T by eq (7)).
  *   NSF_RA  recompute all: no derivative arrays; every derivative occurrence
- *           is its finite-difference formula; p, T by eqs (8)-(9).
+ *           is its finite-difference formula; p, T by eqs (9)-(10).
  *   NSF_SN  store none: as RA, each derivative evaluated once into a
  *           thread-local value and reused.
  *   NSF_RS  recompute some: the nine velocity gradients du_i/dx_j stored in

@@ -14,10 +14,16 @@
  *
  * Pins (checked by the CPU tests, not by comparison with the GPU):
  * closed-form modified wavenumbers of the first, second and cross
- * derivatives; exact initial kinetic energy, enstrophy and energy-residual
- * mean of the Taylor-Green state; the initial kinetic-energy decay rate;
- * discrete conservation of mass and momentum; third-order time accuracy;
- * dense Kronecker-operator brute force on small grids.
+ * derivatives; exact initial kinetic energy, enstrophy, extrema and
+ * energy-residual mean of the Taylor-Green state; the initial kinetic-energy
+ * decay rate; fourth-order convergence of every residual field to the exact
+ * residual of the continuous equations (symbolic, divergence form); the exact
+ * discrete residual of one-dimensional compressive waves (trigonometric
+ * polynomials through the modified wavenumbers), which fixes the skew split
+ * and the pressure work of the energy equation; discrete conservation of
+ * mass and momentum; third-order time accuracy; dense Kronecker-operator
+ * brute force on small grids. Copies with a planted mistake in any of these
+ * terms fail at least one pin.
  */
 #include <math.h>
 #include <stdint.h>

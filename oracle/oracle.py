@@ -12,6 +12,7 @@ selects the C instantiation: ``"d"`` (float64) or ``"ld"`` (x87 extended,
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -47,32 +48,51 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def load(path: str):
+    """Open a compiled oracle library and declare its entry points."""
+    L = ctypes.CDLL(path)
+    i, d, u64, vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
+    L.oracle_splitmix64.restype = u64
+    L.oracle_splitmix64.argtypes = [u64, u64]
+    L.oracle_splitmix_uniform.restype = d
+    L.oracle_splitmix_uniform.argtypes = [u64, u64]
+    L.oracle_set_threads.argtypes = [i]
+    L.oracle_get_threads.restype = i
+    for s in ("_d", "_ld"):
+        getattr(L, "oracle_init" + s).argtypes = [i, i, i, d, d, d, i, d, u64, d, d, d, vp]
+        getattr(L, "oracle_init_slab" + s).argtypes = [i, i, i, i, i, d, d, d, i, d, u64, d, d,
+                                                      d, vp]
+        getattr(L, "oracle_rhs_slab" + s).argtypes = [i, i, i, i, d, d, d, d, vp, vp]
+        getattr(L, "oracle_prims" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+        getattr(L, "oracle_rhs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+        getattr(L, "oracle_rhs_planes" + s).argtypes = [i, i, i, d, d, d, d, vp, vp, i, i]
+        getattr(L, "oracle_rk_step" + s).argtypes = [i, i, i, d, d, d, d, d, i, vp]
+        getattr(L, "oracle_diag" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+        getattr(L, "oracle_derivs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
+        getattr(L, "oracle_rk_step_rounded" + s).argtypes = [i, i, i, d, d, d, d, d, i, vp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        i, d, u64, vp = ctypes.c_int, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
-        L.oracle_splitmix64.restype = u64
-        L.oracle_splitmix64.argtypes = [u64, u64]
-        L.oracle_splitmix_uniform.restype = d
-        L.oracle_splitmix_uniform.argtypes = [u64, u64]
-        L.oracle_set_threads.argtypes = [i]
-        L.oracle_get_threads.restype = i
-        for s in ("_d", "_ld"):
-            getattr(L, "oracle_init" + s).argtypes = [i, i, i, d, d, d, i, d, u64, d, d, d, vp]
-            getattr(L, "oracle_init_slab" + s).argtypes = [i, i, i, i, i, d, d, d, i, d, u64, d, d,
-                                                          d, vp]
-            getattr(L, "oracle_rhs_slab" + s).argtypes = [i, i, i, i, d, d, d, d, vp, vp]
-            getattr(L, "oracle_prims" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
-            getattr(L, "oracle_rhs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
-            getattr(L, "oracle_rhs_planes" + s).argtypes = [i, i, i, d, d, d, d, vp, vp, i, i]
-            getattr(L, "oracle_rk_step" + s).argtypes = [i, i, i, d, d, d, d, d, i, vp]
-            getattr(L, "oracle_diag" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
-            getattr(L, "oracle_derivs" + s).argtypes = [i, i, i, d, d, d, d, vp, vp]
-        _lib = L
+        _lib = load(_LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def library(path: str):
+    """Route every call of this module to another build of the oracle (the
+    tests use it to run the pins on copies with a planted mistake)."""
+    global _lib
+    saved = lib()
+    _lib = load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
 
 
 def _dtype(prec: str):
@@ -153,7 +173,7 @@ def prims(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
 
 
 def rhs(q: np.ndarray, phys, prec: str = "d") -> np.ndarray:
-    """Residual R(q) (Section 2, eqs (1)-(5), (10))."""
+    """Residual R(q) (Section 2, eqs (1)-(5), (8))."""
     q = np.ascontiguousarray(q, dtype=_dtype(prec))
     nx, ny, nz = _shape_of(q)
     r = np.empty_like(q)
@@ -178,6 +198,17 @@ def rk_step(q: np.ndarray, phys, dt: float, nsteps: int = 1, prec: str = "d") ->
     nx, ny, nz = _shape_of(q)
     getattr(lib(), "oracle_rk_step_" + prec)(nx, ny, nz, *_phys(phys), float(dt), int(nsteps),
                                             _ptr(q))
+    return q
+
+
+def rk_step_rounded(q: np.ndarray, phys, dt: float, nsteps: int = 1,
+                    prec: str = "d") -> np.ndarray:
+    """rk_step with each substep's input state rounded to float32 (the
+    single-precision state of the FP32 form; the accumulator keeps prec)."""
+    q = np.array(q, dtype=_dtype(prec), order="C", copy=True)
+    nx, ny, nz = _shape_of(q)
+    getattr(lib(), "oracle_rk_step_rounded_" + prec)(nx, ny, nz, *_phys(phys), float(dt),
+                                                    int(nsteps), _ptr(q))
     return q
 
 

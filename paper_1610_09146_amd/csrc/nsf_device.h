@@ -93,7 +93,7 @@ __device__ __forceinline__ T fast_rcp(T x) {
 #endif
 }
 
-// Primitive variables from one point's conservative values, eqs (8)-(9):
+// Primitive variables from one point's conservative values, eqs (9)-(10):
 // u_a = (rho u_a)/rho, p = (gamma-1)(rho E - rho|u|^2/2), T = gamma Ma^2 p/rho.
 // One reciprocal of rho per point.
 template <typename T>
@@ -133,7 +133,7 @@ struct Terms {
     T cross[3];
 };
 
-// Residual assembly (Section 2): skew-symmetric convection eq (10) with
+// Residual assembly (Section 2): skew-symmetric convection eq (8) with
 // phi = 1, u_a, E; pressure gradient and pressure work in divergence form;
 // viscous force expanded to second derivatives,
 //   V_a = (1/Re)[sum_b D2_b u_a + (D2_a u_a + sum_{k!=a} D_a G_kk)/3];

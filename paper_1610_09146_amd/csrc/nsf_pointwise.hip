@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kBlock) k_init(Dims d, InitParams p, T* __rest
     }
 }
 
-// Fused primitives, eqs (8)-(9): u, v, w, p, T from q in one pass.
+// Fused primitives, eqs (9)-(10): u, v, w, p, T from q in one pass.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_prims(Dims d, Coef<T> c, const T* __restrict__ q,
                                                   T* __restrict__ prim) {

@@ -353,7 +353,7 @@ def test_shear_wave_viscous_force_and_work():
 def test_uniform_translation_convective_terms():
     # rho = 1 + e sin(k z), uniform velocity (0, 0, U), p constant:
     #   R(rho) = -U D_z rho,  R(rho w) = -U^2 D_z rho,  R(rho u) = R(rho v) = 0
-    # (skew-symmetric split eq (10) with D_z U = 0)
+    # (skew-symmetric split eq (8) with D_z U = 0)
     N, k, e, U = 16, 3, 0.1, 0.7
     X, Y, Z = grid((8, 10, N))
     h = 2 * np.pi / N
