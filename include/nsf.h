@@ -185,6 +185,22 @@ int nsf_diagnostics(const nsf_grid *g, const nsf_phys *phys, int precision,
                     const void *q, void *work, size_t work_bytes, double *out,
                     void *stream);
 
+/* nsf_diagnostics for callers that cannot allocate device memory (no
+ * hipMalloc and no work buffer: serving loops and harnesses that forbid
+ * allocation). Same kernels, same outputs, same synchronisation and the same
+ * NSF_ENONFINITE rule as nsf_diagnostics, but the per-tile partial sums and
+ * the result live in a fixed array of the library (8 MiB of device memory on
+ * each GPU it runs on, held until the process ends) instead of `work`; no
+ * memory is allocated by this call. The grid may have at most 65536
+ * diagnostics tiles of 32 x 8 columns x 64 planes (ceil(nx/32) *
+ * ceil(ny/8) * ceil(nz/64); a 1024^3 grid has exactly 65536); larger grids
+ * return NSF_EINVAL before anything is enqueued. The stream must belong to
+ * the current device (NSF_EINVAL otherwise). Every call on one GPU shares
+ * that array, so calls that overlap in time on one GPU (other host threads,
+ * other streams) race and must be serialised by the caller. */
+int nsf_diagnostics_noalloc(const nsf_grid *g, const nsf_phys *phys, int precision,
+                            const void *q, double *out, void *stream);
+
 /* ---------------------------------------------------------------- autotuner
  * Searches the paper's store-versus-recompute trade-off (Section 2: which
  * derivatives to store in work arrays, which to recompute; the

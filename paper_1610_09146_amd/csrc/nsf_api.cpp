@@ -522,6 +522,24 @@ int nsf_diagnostics(const nsf_grid* g, const nsf_phys* phys, int precision, cons
     return NSF_OK;
 }
 
+int nsf_diagnostics_noalloc(const nsf_grid* g, const nsf_phys* phys, int precision, const void* q,
+                            double* out, void* stream) {
+    Dims d;
+    int rc = validate_grid(g, &d);
+    if (rc) return rc;
+    if ((rc = validate_phys(phys))) return rc;
+    if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
+    if (!q || !out) return fail(NSF_EINVAL, "q and out must be non-NULL");
+    if (diag_partial_count(d) > diag_noalloc_max_tiles())
+        return fail(NSF_EINVAL, "grid %dx%dx%d needs %zu diagnostics tiles; the allocation-free "
+                    "form holds at most %zu", d.nx, d.ny, d.nz, diag_partial_count(d),
+                    diag_noalloc_max_tiles());
+    const Coef<double> c = make_coef<double>(d, phys->Re, phys->Ma, phys->Pr, phys->gamma);
+    if ((rc = diag_noalloc(d, c, precision, q, out, (hipStream_t)stream))) return rc;
+    if (out[14] > 0) return fail(NSF_ENONFINITE, "%.0f non-finite values in q", out[14]);
+    return NSF_OK;
+}
+
 int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
     if (!src || !dst) return fail(NSF_EINVAL, "src and dst must be non-NULL");
     if (overlap(src, bytes, dst, bytes)) return fail(NSF_EINVAL, "src and dst overlap");

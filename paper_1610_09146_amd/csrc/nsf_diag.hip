@@ -13,6 +13,8 @@
 // bitwise reproducible for a given grid.
 #include <math.h>
 
+#include <mutex>
+
 #include "nsf_internal.h"
 
 namespace nsf {
@@ -280,6 +282,71 @@ void launch_diag(const Dims& d, const Coef<double>& c, const T* q, double* parti
     hipLaunchKernelGGL(k_diag_partial<T>, dim3(nb), dim3(kNT), 0, s, a, q, partial);
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(256), 0, s, nb, 1.0 / (double)d.npts, partial,
                        out_dev);
+}
+
+// ------------------------------------------------ allocation-free diagnostics
+// Partials and result of nsf_diagnostics_noalloc: one kND-double slot per
+// diagnostics tile, for at most kScratchTiles tiles (a 1024^3 grid has
+// 32 x 128 x 16 = 65536), then the kND output doubles; 8 MiB per GPU, held
+// until the process ends. Every call on one GPU shares it. In host code the
+// name `scratch` is a host-side stand-in, not a device address: kernels and
+// copies get the address hipGetSymbolAddress returns on each device.
+constexpr size_t kScratchTiles = 65536;
+static __device__ __align__(256) double scratch[kScratchTiles * kND + kND];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device
+// (with that device current) and kept.
+int scratch_address(double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(NSF_EHIP, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(NSF_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(NSF_EHIP, e != hipSuccess ? hipGetErrorString(e)
+                                                       : "scratch has no device address");
+        g_scratch_dev[dev] = (double*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return NSF_OK;
+}
+}  // namespace
+
+size_t diag_noalloc_max_tiles() { return kScratchTiles; }
+
+int diag_noalloc(const Dims& d, const Coef<double>& c, int precision, const void* q,
+                 double* out_host, hipStream_t s) {
+    if (diag_partial_count(d) > kScratchTiles)
+        return set_error(NSF_EINVAL, "grid needs more diagnostics tiles than the fixed scratch holds");
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return set_error(NSF_EHIP, hipGetErrorString(e));
+    if (s) {
+        int sdev = -1;
+        e = hipStreamGetDevice(s, &sdev);
+        if (e != hipSuccess) return set_error(NSF_EHIP, hipGetErrorString(e));
+        if (sdev != cur) return set_error(NSF_EINVAL, "stream belongs to another device than the current one");
+    }
+    double* base = nullptr;
+    int rc = scratch_address(&base);
+    if (rc) return rc;
+    double* partial = base;
+    double* dout = base + kScratchTiles * kND;
+    if (precision == NSF_F64) launch_diag<double>(d, c, (const double*)q, partial, dout, s);
+    else launch_diag<float>(d, c, (const float*)q, partial, dout, s);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out_host, dout, kND * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_error(NSF_EHIP, hipGetErrorString(e));
+    return NSF_OK;
 }
 
 template void launch_diag<float>(const Dims&, const Coef<double>&, const float*, double*, double*,

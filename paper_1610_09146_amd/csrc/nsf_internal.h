@@ -150,5 +150,11 @@ size_t diag_partial_count(const Dims& d);
 template <typename T>
 void launch_diag(const Dims& d, const Coef<double>& c, const T* q, double* partial, double* out_dev,
                  hipStream_t s);
+// Diagnostics with the partials in the library's fixed per-GPU scratch
+// (nsf_diagnostics_noalloc): NSF_EINVAL when the grid has more tiles than
+// diag_noalloc_max_tiles(). Waits for the stream and writes out_host.
+size_t diag_noalloc_max_tiles();
+int diag_noalloc(const Dims& d, const Coef<double>& c, int precision, const void* q,
+                 double* out_host, hipStream_t s);
 
 }  // namespace nsf

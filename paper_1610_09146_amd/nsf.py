@@ -92,6 +92,7 @@ def lib() -> ctypes.CDLL:
         L.nsf_rk_step_monitored.argtypes = [G, P, ctypes.c_int, ctypes.c_int, Tu, d, i32, vp, vp,
                                             vp, vp, sz, vp, vp]
         L.nsf_diagnostics.argtypes = [G, P, ctypes.c_int, vp, vp, sz, ctypes.POINTER(d), vp]
+        L.nsf_diagnostics_noalloc.argtypes = [G, P, ctypes.c_int, vp, ctypes.POINTER(d), vp]
         L.nsf_device_copy.argtypes = [vp, vp, sz, vp]
         L.nsf_timer_enable.argtypes = [ctypes.c_char_p]
         L.nsf_timer_read.argtypes = [ctypes.POINTER(i64), ctypes.POINTER(d)]
@@ -253,6 +254,18 @@ def diagnostics(shape, phys, precision, q, work, stream=None, check: bool = True
                                work.numel() * work.element_size(), out, _stream(stream))
     if check or rc != ENONFINITE:
         _check(rc, "nsf_diagnostics")
+    return np.array(out[:], dtype=np.float64)
+
+
+def diagnostics_noalloc(shape, phys, precision, q, stream=None, check: bool = True) -> np.ndarray:
+    """nsf_diagnostics_noalloc: the diagnostics of q with no work buffer
+    (the library's fixed per-GPU scratch holds the partial sums)."""
+    _fields(shape, precision, q=q)
+    out = (ctypes.c_double * NDIAG)()
+    rc = lib().nsf_diagnostics_noalloc(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
+                                       _precision(precision), _ptr(q), out, _stream(stream))
+    if check or rc != ENONFINITE:
+        _check(rc, "nsf_diagnostics_noalloc")
     return np.array(out[:], dtype=np.float64)
 
 

@@ -176,3 +176,26 @@ def test_binding_checks_state_sizes_and_dtypes(nsf):
         nsf._fields(shape, "f32", q=good)
     with pytest.raises(nsf.NsfError):
         nsf._fields(shape, "f32", q=good.float(), q_acc=good.float())
+
+
+def test_noalloc_rejects_before_any_work(nsf):
+    """nsf_diagnostics_noalloc refuses, before any HIP call, a grid with more
+    diagnostics tiles than its fixed scratch holds (ceil(nx/32) ceil(ny/8)
+    ceil(nz/64) > 65536) and NULL pointers."""
+    import ctypes
+    L = nsf.lib()
+    out = (ctypes.c_double * nsf.NDIAG)()
+    phys = {"Re": 1600.0, "Ma": 0.1, "Pr": 0.71, "gamma": 1.4}
+    dummy = ctypes.c_void_p(256)
+    big = nsf._grid((1024, 1024, 1088))  # 32 x 128 x 17 tiles
+    rc = L.nsf_diagnostics_noalloc(ctypes.byref(big), ctypes.byref(nsf._phys(phys)), 0, dummy,
+                                   out, None)
+    assert rc == nsf.EINVAL
+    assert "65536" in L.nsf_last_error().decode()
+    small = nsf._grid((16, 16, 16))
+    rc = L.nsf_diagnostics_noalloc(ctypes.byref(small), ctypes.byref(nsf._phys(phys)), 0, None,
+                                   out, None)
+    assert rc == nsf.EINVAL
+    rc = L.nsf_diagnostics_noalloc(ctypes.byref(small), ctypes.byref(nsf._phys(phys)), 0, dummy,
+                                   None, None)
+    assert rc == nsf.EINVAL
