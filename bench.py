@@ -130,15 +130,21 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_famili
             fam_ms[fam] = ms
         nsf.timer_enable(None)
     dominant = max(fam_ms, key=fam_ms.get) if fam_ms else None
+    # per-launch time of the dominant family (roofline): HIP events around
+    # each of its launches, in an untimed pass of the same number of steps
+    kcount, kms = 0, 0.0
     if dominant:
         nsf.timer_enable(dominant)
+        s.step_monitored(dt, steps, mon)
+        torch.cuda.synchronize()
+        kcount, kms = nsf.timer_read()
+        nsf.timer_enable(None)
+    # the timed region: no per-launch timer
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step_monitored(dt, steps, mon)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kcount, kms = nsf.timer_read() if dominant else (0, 0.0)
-    nsf.timer_enable(None)
     monitor = mon.cpu().numpy().reshape(-1, 2)[:steps]
     diag = s.diagnostics()  # the final state, outside the timed region
     ms_per_step = (t1 - t0) * 1e3 / steps
@@ -311,6 +317,49 @@ def roofline_of(res, precision):
             "frac_of_copy": round(achieved / COPY_PEAK["GBps"], 4) if COPY_PEAK else None}
 
 
+def cpu_sizes(W):
+    """The oracle on whole small grids: one residual and one RK step at 64^3
+    and 128^3 with one thread and with every host thread, and one residual
+    at 256^3 with every host thread (pt-RHS/s)."""
+    from oracle import oracle as O
+    phys = W.TGV_PHYS
+    all_threads = O.get_threads()
+    rows = []
+    for n, threads, what in ((64, 1, "rhs"), (64, 1, "rk_step"), (64, all_threads, "rhs"),
+                             (64, all_threads, "rk_step"), (128, 1, "rhs"),
+                             (128, 1, "rk_step"), (128, all_threads, "rhs"),
+                             (128, all_threads, "rk_step"), (256, all_threads, "rhs")):
+        q = O.init((n, n, n), phys, W.tgv_pointwise(1610, 1e-3))
+        O.set_threads(threads)
+        t0 = time.perf_counter()
+        if what == "rhs":
+            O.rhs(q, phys)
+            evals = n ** 3
+        else:
+            O.rk_step(q, phys, W.tgv_dt(n), 1)
+            evals = 3 * n ** 3
+        dt_s = time.perf_counter() - t0
+        rows.append({"n": n, "call": what, "threads": threads, "seconds": round(dt_s, 3),
+                     "pt_rhs_per_s": evals / dt_s})
+    O.set_threads(all_threads)
+    return rows
+
+
+def cpu_host():
+    """Host CPU model name and logical core count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(W, budget_s=12.0, n=512, planes_per_call=8):
     """Oracle (plain C, FP64) residual on consecutive z-slabs of the same
     512^3 Taylor-Green grid until about budget_s seconds have elapsed."""
@@ -327,7 +376,8 @@ def cpu_baseline(W, budget_s=12.0, n=512, planes_per_call=8):
         k0 += planes_per_call
     return {"value": done_pts / spent, "unit": "pt-RHS/s", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle residual of z-planes 0..{k0 - 1} of the {n}^3 Taylor-Green "
-                      f"grid ({done_pts} point-RHS in {spent:.1f} s, {threads} threads)"}
+                      f"grid ({done_pts} point-RHS in {spent:.1f} s, {threads} threads)",
+            "host": cpu_host(), "sizes": cpu_sizes(W)}
 
 
 def main() -> int:
