@@ -37,10 +37,14 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 FAMILY_BYTES = {
     "prims": (80, 40),            # q -> u, v, w, p, T
     "update": (160, 120),         # r, q_acc -> q, q_acc
-    "ra_naive": (120, 60),        # q, prims -> r
-    "ra_zsweep": (120, 60),       # q, prims -> r
-    "ra_fused": (160, 120),       # q, q_acc -> q_next, q_acc
+    "ra_naive": (120, 60),        # q, prims -> r (untiled, RA and SN)
+    "ra_zsweep": (120, 60),       # RA: q, prims -> r
+    "sn_zsweep": (120, 60),       # SN: q, prims -> r
+    "ra_fused": (160, 120),       # RA: q, q_acc -> q_next, q_acc
     "ra_fused_mon": (160, 120),   # the same, plus per-tile KE / enstrophy sums
+    "sn_fused": (160, 120),       # SN: q, q_acc -> q_next, q_acc
+    "sn_fused_mon": (160, 120),   # the same, plus per-tile KE / enstrophy sums
+    "rs_zsweep": (192, 96),       # RS: q, prims, 9 gradients -> r
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
     "ss_grad": (96, 48),          # u, v, w -> 9 gradients
@@ -89,14 +93,15 @@ def families(variant, tune):
     if variant == "BL":
         return ["prims", "bl_product", "bl_deriv", "bl_assemble", "update", "diag"]
     if variant in ("RA", "SN"):
+        k = variant.lower()
         if tune and tune.get("fuse"):
-            return ["ra_fused", "ra_fused_mon"]
+            return [f"{k}_fused", f"{k}_fused_mon"]
         if tune and tune.get("naive"):
             return ["prims", "ra_naive", "update", "diag"]
-        return ["prims", "ra_zsweep", "update", "diag"]
+        return ["prims", f"{k}_zsweep", "update", "diag"]
     if tune and tune.get("naive"):
         return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
-    return ["prims", "ss_grad", "ss_zsweep", "update", "diag"]
+    return ["prims", "ss_grad", "rs_zsweep" if variant == "RS" else "ss_zsweep", "update", "diag"]
 
 
 def log(msg: str) -> None:
@@ -182,7 +187,7 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     nsf.timer_enable(None)
     d = b.diagnostics()
     nitems, nblocks = b.info()
-    per_pt = FAMILY_BYTES["ra_fused"][0 if precision == "f64" else 1] * 3
+    per_pt = FAMILY_BYTES["sn_fused"][0 if precision == "f64" else 1] * 3
     avg_s = ms / max(c, 1) / 1e3
     out = {
         "instances": len(insts), "points": pts, "precision": precision, "steps": steps,
@@ -199,10 +204,10 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     del b
     torch.cuda.empty_cache()
     # the same ensemble advanced by the plain single-grid FP64/FP32 path, one
-    # instance after another (fused RA, one rk_step call per instance)
+    # instance after another (fused SN, one rk_step call per instance)
     solvers = []
     for inst in insts:
-        sv = nsf.Solver(inst["shape"], inst["phys"], "RA", precision, tune={"fuse": 1})
+        sv = nsf.Solver(inst["shape"], inst["phys"], "SN", precision, tune={"fuse": 1})
         sv.init(inst["tgv"])
         sv.step(inst["dt"], 1)
         solvers.append(sv)
@@ -225,7 +230,7 @@ def precision_errors(nsf, torch, W, n, steps, tuned):
     enstrophy, the KE change over the run, and per-field max-norms."""
     out = {}
     for prec in ("f64", "f32"):
-        var = tuned[prec]["variant"] if tuned else "RA"
+        var = tuned[prec]["variant"] if tuned else "SN"
         tune = tuned[prec]["tune"] if tuned else {"fuse": 1}
         s = nsf.Solver((n, n, n), W.TGV_PHYS, var, prec, tune=tune)
         s.init(W.tgv_unperturbed())
@@ -441,30 +446,43 @@ def main() -> int:
     if not args.no_extras:
         for name, v, prec, k, tune in (("BL_f64", "BL", "f64", 3, None),
                                        ("SS_f64", "SS", "f64", 5, None),
+                                       ("RS_f64", "RS", "f64", 5, None),
+                                       ("SN_f64_stored_prims", "SN", "f64", 5, None),
                                        ("RA_f64_stored_prims", "RA", "f64", 5, None),
-                                       ("RA_f32_fused", "RA", "f32", 10, {"fuse": 1})) + (
+                                       ("RA_f64_fused", "RA", "f64", 5, {"fuse": 1}),
+                                       ("SN_f32_fused", "SN", "f32", 10, {"fuse": 1})) + (
                 (("f32_autotuned", tuned["f32"]["variant"], "f32", 10, tuned["f32"]["tune"]),)
                 if tuned else ()):
             log(f"extra: {name}")
             r = run_variant(nsf, torch, W, n, v, prec, k, 1, tune=tune)
             r["roofline"] = roofline_of(r, prec)
             extras[name] = r
-        # 256^3, every variant, pointwise +-1e-3 perturbation (seed 1610), 100 steps
-        for name, v, tune in (("BL", "BL", None), ("SS", "SS", None),
-                              ("RA_stored_prims", "RA", None), ("RA_fused", "RA", {"fuse": 1})):
-            log(f"extra: 256^3 {name}")
-            r = run_variant(nsf, torch, W, 256, v, "f64", 100, 1, tune=tune,
-                            tgv=W.tgv_pointwise(1610, 1e-3))
-            r["roofline"] = roofline_of(r, "f64")
-            extras[f"n256_{name}_f64"] = r
+        # the paper's Table 1 on one MI355X: the five algorithms in the
+        # paper's form (stored primitives, separate update) and the fused RA
+        # and SN, FP64, at 64^3, 128^3 and 256^3, pointwise +-1e-3
+        # perturbation (seed 1610), 100 steps
+        table = []
+        for nt in (64, 128, 256):
+            for name, v, tune in (("BL", "BL", None), ("RA", "RA", None), ("RS", "RS", None),
+                                  ("SN", "SN", None), ("SS", "SS", None),
+                                  ("RA_fused", "RA", {"fuse": 1}), ("SN_fused", "SN", {"fuse": 1})):
+                log(f"extra: {nt}^3 {name}")
+                r = run_variant(nsf, torch, W, nt, v, "f64", 100, 1, tune=tune,
+                                tgv=W.tgv_pointwise(1610, 1e-3))
+                rl = roofline_of(r, "f64")
+                table.append({"n": nt, "algorithm": name, "ms_per_step": round(r["ms_per_step"], 4),
+                              "pt_rhs_per_s": r["pt_rhs_per_s"], "dominant": r["dominant"],
+                              "dominant_frac_of_8TBs": rl["frac"] if rl else None,
+                              "family_ms_one_step": r["family_ms_one_step"]})
+        extras["table1_f64"] = table
         # the largest single-GPU grid, 1024^3 (about 215 GB), when it fits
         torch.cuda.empty_cache()
-        need = nsf.workspace_bytes((1024,) * 3, "RA", "f64", {"fuse": 1}) + 15 * 1024 ** 3 * 8
+        need = nsf.workspace_bytes((1024,) * 3, "SN", "f64", {"fuse": 1}) + 15 * 1024 ** 3 * 8
         if torch.cuda.mem_get_info()[0] > need + (2 << 30):
-            log("extra: 1024^3 RA fused f64")
-            r = run_variant(nsf, torch, W, 1024, "RA", "f64", 3, 1, tune={"fuse": 1})
+            log("extra: 1024^3 SN fused f64")
+            r = run_variant(nsf, torch, W, 1024, "SN", "f64", 3, 1, tune={"fuse": 1})
             r["roofline"] = roofline_of(r, "f64")
-            extras["n1024_RA_fused_f64"] = r
+            extras["n1024_SN_fused_f64"] = r
         for prec in ("f64", "f32"):
             log(f"extra: batch64 {prec}")
             extras[f"batch64_{prec}"] = run_batch(nsf, torch, W, prec, 10)

@@ -56,21 +56,30 @@ typedef enum {
     NSF_ENONFINITE = -5    /* diagnostics found NaN/Inf in the state   */
 } nsf_status;
 
-/* The paper's algorithms (Section 2):
+/* The paper's algorithms (Section 2), each a kernel sequence of its own:
  *   NSF_BL  baseline: every first/second derivative is a grid-sized work
  *           array; products staged in one reused work array; primitives in
  *           three separate loops (u_i, then p by eq (6), then T by eq (7)).
- *   NSF_RA  recompute all: no derivative arrays; every derivative occurrence
- *           is its finite-difference formula; p, T by eqs (9)-(10).
- *   NSF_SN  store none: as RA, each derivative evaluated once into a
- *           thread-local value and reused.
+ *   NSF_RA  recompute all: no derivative arrays; the five equations are
+ *           evaluated one after another and each forms every derivative it
+ *           uses from the staged grid values, nothing being carried from one
+ *           equation to the next (cross derivatives as nested stencils);
+ *           p, T by eqs (9)-(10).
+ *   NSF_SN  store none: no derivative arrays; each derivative is formed once
+ *           per point into a thread-local value and reused wherever it
+ *           occurs (the velocity gradients, for instance, in all five
+ *           equations).
  *   NSF_RS  recompute some: the nine velocity gradients du_i/dx_j stored in
- *           work arrays, the rest recomputed inline.
- *   NSF_SS  store some: as RS, the non-stored derivatives held in
- *           thread-local values (the paper's fastest CPU algorithm). */
+ *           work arrays by their own kernel and read wherever they occur;
+ *           the other derivatives formed where used, equation by equation.
+ *   NSF_SS  store some: the nine velocity gradients stored as in RS, the
+ *           other derivatives formed once into thread-local values.
+ * In every algorithm the primitive variables are a stored array and the RK
+ * update its own kernel (the paper's structure); RA and SN also have the
+ * fused form (nsf_tuning.fuse). */
 typedef enum { NSF_BL = 0, NSF_RA = 1, NSF_SS = 2, NSF_SN = 3, NSF_RS = 4, NSF_AUTO = 5 } nsf_variant;
 /* NSF_AUTO: the algorithm and tuning that nsf_autotune (or nsf_tune_load)
- * recorded for this grid and precision in this process; RA with the fused
+ * recorded for this grid and precision in this process; SN with the fused
  * stage kernel if nothing was recorded. The tuning argument is ignored. */
 typedef enum { NSF_F64 = 0, NSF_F32 = 1 } nsf_precision;
 
@@ -115,7 +124,9 @@ typedef struct {
  *         update a separate kernel, as in the paper; 1 = primitives
  *         recomputed inside the residual tile and the RK update fused into
  *         the residual kernel (needs the ping-pong copy of q in `work`).
- *   naive: 1 = use the untiled per-point kernels (reference GPU path). */
+ *   naive: 1 = use the untiled per-point kernels (reference GPU path): one
+ *         kernel per store set, so RA and SN run the same untiled kernel,
+ *         and so do RS and SS. */
 typedef struct {
     int32_t block_x, block_y, zchunk, fuse, naive;
     int32_t reserved[3];

@@ -141,10 +141,10 @@ bool is_variant(int v) { return v >= NSF_BL && v <= NSF_AUTO; }
 void resolve(const Dims& d, int precision, int* variant, const nsf_tuning** tune,
              nsf_tuning* store) {
     if (*variant != NSF_AUTO) return;
-    int v = NSF_RA;
+    int v = NSF_SN;
     std::memset(store, 0, sizeof *store);
     if (!tune_lookup(d, precision, &v, store)) {
-        v = NSF_RA;
+        v = NSF_SN;
         store->fuse = 1;
     }
     *variant = v;
@@ -277,7 +277,8 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
         case NSF_SN:
             launch_prims<T>(d, c, q, prim, s);
             if (tune && tune->naive) launch_ra_naive<T>(d, c, q, prim, r, s);
-            else launch_ra_zsweep<T>(d, c, q, prim, r, zchunk_of(d, tune), tile_y_of(d, tune, sizeof(T)), s);
+            else launch_ra_zsweep<T>(d, c, q, prim, r, zchunk_of(d, tune), tile_y_of(d, tune, sizeof(T)), s,
+                                     variant == NSF_RA);
             break;
         case NSF_SS:
         case NSF_RS: {
@@ -289,7 +290,7 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
             } else {
                 launch_ss_grad<T>(d, c, prim, grad, s);
                 launch_ss_zsweep<T>(d, c, q, prim, grad, r, zchunk_of(d, tune),
-                                    tile_y_of(d, tune, sizeof(T)), s);
+                                    tile_y_of(d, tune, sizeof(T)), s, variant == NSF_RS);
             }
             break;
         }
@@ -325,7 +326,7 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.last = st == 2;
                 const bool mon = monitor && st == 0;
                 launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s,
-                                   mon ? mpart : nullptr);
+                                   mon ? mpart : nullptr, variant == NSF_RA);
                 if (mon)
                     launch_monitor_final(mpart, sweep_tiles(d, zc, ty), inv_n, monitor + 2 * step, s);
             }
@@ -551,7 +552,8 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ra_fused_mon,"
-    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,diag,copy,ra_batch,batch_step";
+    "sn_zsweep,sn_fused,sn_fused_mon,ss_grad_naive,ss_naive,ss_grad,ss_zsweep,rs_zsweep,diag,copy,"
+    "ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

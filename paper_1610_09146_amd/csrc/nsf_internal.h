@@ -120,24 +120,31 @@ void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* off
                      int nblocks, int tile_y, hipStream_t s);
 template <typename T>
 int batch_blocks_per_cu(int tile_y);
+// Residual from stored primitives, no derivative arrays: recompute = true is
+// the recompute-all algorithm RA (every derivative formed where a term uses
+// it, equation by equation), false the store-none algorithm SN (every
+// derivative formed once per point into thread-local values).
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, int tile_y, hipStream_t s);
-// SS residual: the tiled sweep with the velocity gradients and D_a(G_cc)
-// read from the nine stored gradient arrays.
+                      int zchunk, int tile_y, hipStream_t s, bool recompute);
+// Residual with the velocity gradients and D_a(G_cc) read from the nine
+// stored gradient arrays: recompute = true is the recompute-some algorithm
+// RS (the other derivatives formed where used, equation by equation), false
+// the store-some algorithm SS (thread-local values).
 template <typename T>
 void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
-                      T* r, int zchunk, int tile_y, hipStream_t s);
+                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute);
 // SS gradient loop: G_ab = D_b u_a into nine arrays (z-marching tiles).
 template <typename T>
 void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hipStream_t s);
-// Fused RA stage: primitives recomputed in-tile, residual, and the RK stage
+// Fused stage with no derivative arrays (RA with recompute = true, SN
+// otherwise): primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),
 // q_acc += B dt R. qout must not alias q.
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s,
-                     double* mpart = nullptr);
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s, double* mpart,
+                     bool recompute);
 
 // Fold per-tile (KE, enstrophy) sums in tile order into out2[0..1] as means.
 void launch_monitor_final(const double* mpart, int ntiles, double inv_n, double* out2,

@@ -109,9 +109,13 @@ std::vector<nsf_tune_result> candidates(const nsf_grid* g, int flags) {
         if (zc <= g->nz) zcs.push_back(zc);
     if (zcs.empty()) zcs.push_back(g->nz);
     for (int by : {8, 16}) {
-        for (int zc : zcs) add(NSF_RA, by, zc, 1, 0);
-        add(NSF_RA, by, zcs.back() >= 64 ? 64 : zcs.back(), 0, 0);
-        add(NSF_SS, by, zcs.back() >= 64 ? 64 : zcs.back(), 0, 0);
+        const int zd = zcs.back() >= 64 ? 64 : zcs.back();
+        for (int zc : zcs) add(NSF_SN, by, zc, 1, 0);
+        add(NSF_RA, by, zd, 1, 0);
+        add(NSF_SN, by, zd, 0, 0);
+        add(NSF_RA, by, zd, 0, 0);
+        add(NSF_SS, by, zd, 0, 0);
+        add(NSF_RS, by, zd, 0, 0);
     }
     if (!(flags & NSF_TUNE_QUICK)) {
         add(NSF_BL, 0, 0, 0, 0);
@@ -273,7 +277,7 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
         const double tie = 0.98 * win.pt_rhs_per_s;
         const int es = precision == NSF_F64 ? 8 : 4;
         auto is_default = [&](const nsf_tune_result& r) {
-            return r.variant == NSF_RA && r.tune.fuse && !r.tune.naive &&
+            return r.variant == NSF_SN && r.tune.fuse && !r.tune.naive &&
                    r.tune.block_y == default_tile_y(es, d) && r.tune.zchunk == default_zchunk(d);
         };
         const nsf_tune_result* pick = nullptr;

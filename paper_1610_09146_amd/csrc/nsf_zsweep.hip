@@ -389,6 +389,199 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
            (u[0] * V[0] + u[1] * V[1] + u[2] * V[2]);
 }
 
+// Views of one output plane for the recompute forms: the plane fields of
+// plane z and the velocity of planes z-2 .. z+2 in LDS, each plane with its
+// two-point x-y halo. Strides in elements.
+template <typename T>
+struct RcView {
+    const T* P;      // plane fields rho, rho E, p, T (stored-gradient form: then rho u_a)
+    const T* V[5];   // velocity u, v, w of planes z-2 .. z+2
+    int ownP, ownV;  // the output point in the two layouts
+    int FOP, RSP;    // field and row strides of the plane fields
+    int FOV, RSV;    // field and row strides of the velocity planes
+};
+
+// Residual of one point in the recompute forms (paper Section 2): the
+// recompute-all algorithm RA, and, with the velocity gradients read from
+// their stored arrays, the recompute-some algorithm RS. The five equations
+// are evaluated one after another and every derivative a term needs is
+// formed where the term uses it, from the grid values staged in LDS (x and
+// y stencils, and the cross derivatives with z as nested stencils over the
+// velocity planes) or in the own column's register queue Q (z stencils):
+// nothing is carried from one equation to the next. The empty asm statement
+// with a memory clobber at the start of each equation makes the compiler
+// load the staged values again, so it cannot merge the derivatives of
+// different equations, which would turn the kernel into the thread-local
+// form. A z difference of queue values alone occurs in one equation only, so
+// the queue needs no such fence. Same assembly as the oracle: skew-symmetric
+// convection eq (8) with phi = 1, u_a, E; pressure work -D_j(p u_j); viscous
+// force V_a = (1/Re)[sum_b D2_b u_a + (D2_a u_a + sum_{c != a} D_a G_cc)/3];
+// heat flux kappa sum_b D2_b T; viscous work tau_ab G_ab + u_a V_a.
+// om2 (monitored stage) receives |curl u|^2 from recomputed gradients.
+// Compiler fence for the recompute forms: no load moves across it, so a
+// derivative after it reads its grid values again.
+__device__ __forceinline__ void rc_fence() { asm volatile("" ::: "memory"); }
+// Ties a finished equation's residual to its place between the fences, so the
+// compiler does not sink its arithmetic below them (into the store branch),
+// which would hold every loaded value live until then.
+template <typename T>
+__device__ __forceinline__ void rc_pin(T& x) { asm volatile("" : "+v"(x)); }
+
+template <typename T, bool SS, bool MON, typename PoffF>
+__device__ __forceinline__ void recompute_point(const RcView<T>& v, const Pt<T> Q[5], const T uc[3],
+                                                const Coef<T>& k, const T* grad, size_t n,
+                                                PoffF poff, int z, size_t col, const size_t xnb[4],
+                                                const size_t ynb[4], T R[5], T& om2) {
+    // plane field f at in-plane offset (dx, dy) of plane z
+    auto P = [&](int f, int dx, int dy) -> T { return v.P[f * v.FOP + v.ownP + dx + dy * v.RSP]; };
+    // velocity component c at offset (dx, dy, dz), |dz| <= 2
+    auto U = [&](int c, int dx, int dy, int dz) -> T {
+        return v.V[dz + 2][c * v.FOV + v.ownV + dx + dy * v.RSV];
+    };
+    auto qf = [&](const Pt<T>& q, int f) -> T {
+        switch (f) {
+            case 0: return q.rho;
+            case 1: return q.E;
+            case 2: return q.p;
+            case 3: return q.t;
+            case 4: return q.m0;
+            case 5: return q.m1;
+            default: return q.m2;
+        }
+    };
+    // plane field f at stencil position s (0..4 = offsets -2..2) along B
+    auto F = [&](int f, int B, int s) -> T {
+        if (B == 0) return P(f, s - 2, 0);
+        if (B == 1) return P(f, 0, s - 2);
+        return qf(Q[s], f);
+    };
+    auto Us = [&](int c, int B, int s) -> T {
+        return U(c, B == 0 ? s - 2 : 0, B == 1 ? s - 2 : 0, B == 2 ? s - 2 : 0);
+    };
+    // momentum rho u_a at stencil position s along B (the stored-gradient
+    // form stages the conserved momenta; the others form rho * u_a)
+    auto M = [&](int a, int B, int s) -> T {
+        if constexpr (SS) return F(4 + a, B, s);
+        else return F(0, B, s) * Us(a, B, s);
+    };
+    auto D1 = [&](int B, auto g) -> T { return k.a1[B] * (g(3) - g(1)) + k.a2[B] * (g(4) - g(0)); };
+    auto D2 = [&](int B, auto g) -> T {
+        return k.b0[B] * g(2) + k.b1[B] * (g(3) + g(1)) + k.b2[B] * (g(4) + g(0));
+    };
+    const size_t pz = poff(z);
+    // velocity gradient G_ab = D_b u_a: its stored array (RS) or its difference (RA)
+    auto Gab = [&](int a, int b) -> T {
+        if constexpr (SS) return grad[(3 * a + b) * n + pz + col];
+        else return D1(b, [&](int s) { return Us(a, b, s); });
+    };
+    // D_A(G_cc), A != c: D_A of the stored diagonal gradient (RS), or the
+    // nested difference D_A(D_c u_c) over the staged velocity (RA)
+    auto DG = [&](int A, int c) -> T {
+        if constexpr (SS) {
+            const int comp = 4 * c;
+            auto g = [&](int s) -> T {
+                const int m = s < 2 ? s : s - 1;  // xnb / ynb slot of offset s - 2
+                if (A == 0) return grad[comp * n + pz + xnb[m]];
+                if (A == 1) return grad[comp * n + pz + ynb[m]];
+                return grad[comp * n + poff(z + s - 2) + col];
+            };
+            return D1(A, g);
+        } else {
+            auto inner = [&](int o) -> T {
+                return D1(c, [&](int s) -> T {
+                    int d[3] = {0, 0, 0};
+                    d[A] += o;
+                    d[c] += s - 2;
+                    return U(c, d[0], d[1], d[2]);
+                });
+            };
+            return k.a1[A] * (inner(1) - inner(-1)) + k.a2[A] * (inner(2) - inner(-2));
+        }
+    };
+    auto Visc = [&](int a) -> T {
+        T lap = T(0), d2aa = T(0);
+#pragma unroll
+        for (int B = 0; B < 3; ++B) {
+            const T d2 = D2(B, [&](int s) { return Us(a, B, s); });
+            lap += d2;
+            if (B == a) d2aa = d2;
+        }
+        T cross = T(0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (c != a) cross += DG(a, c);
+        return k.inv_Re * (lap + k.third * (d2aa + cross));
+    };
+    const T rho_c = Q[2].rho;
+    // mass, eq (1)
+    {
+        rc_fence();
+        T S = T(0), div = T(0);
+#pragma unroll
+        for (int B = 0; B < 3; ++B) {
+            S += D1(B, [&](int s) { return M(B, B, s); }) + uc[B] * D1(B, [&](int s) { return F(0, B, s); });
+            div += Gab(B, B);
+        }
+        R[0] = T(-0.5) * (S + rho_c * div);
+        rc_pin(R[0]);
+    }
+    // momentum, eq (2)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rc_fence();
+        T S = T(0), div = T(0);
+#pragma unroll
+        for (int B = 0; B < 3; ++B) {
+            S += D1(B, [&](int s) { return M(a, B, s) * Us(B, B, s); }) +
+                 uc[B] * D1(B, [&](int s) { return M(a, B, s); });
+            div += Gab(B, B);
+        }
+        const T mc = SS ? qf(Q[2], 4 + a) : rho_c * uc[a];
+        R[1 + a] = T(-0.5) * (S + mc * div) - D1(a, [&](int s) { return F(2, a, s); }) + Visc(a);
+        rc_pin(R[1 + a]);
+    }
+    // energy, eq (3)
+    {
+        rc_fence();
+        T S = T(0), pw = T(0), heat = T(0);
+#pragma unroll
+        for (int B = 0; B < 3; ++B) {
+            S += D1(B, [&](int s) { return F(1, B, s) * Us(B, B, s); }) +
+                 uc[B] * D1(B, [&](int s) { return F(1, B, s); });
+            pw += D1(B, [&](int s) { return F(2, B, s) * Us(B, B, s); });
+            heat += D2(B, [&](int s) { return F(3, B, s); });
+        }
+        T G[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) G[a][b] = Gab(a, b);
+        const T div = G[0][0] + G[1][1] + G[2][2];
+        T gg = T(0), gt = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                gg += G[a][b] * G[a][b];
+                gt += G[a][b] * G[b][a];
+            }
+        T vw = T(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vw += uc[a] * Visc(a);
+        R[4] = T(-0.5) * (S + Q[2].E * div) - pw + k.kappa * heat +
+               k.inv_Re * (gg + gt - k.two_thirds * div * div) + vw;
+        rc_pin(R[4]);
+    }
+    if constexpr (MON) {
+        rc_fence();
+        const T ox = Gab(2, 1) - Gab(1, 2);
+        const T oy = Gab(0, 2) - Gab(2, 0);
+        const T oz = Gab(1, 0) - Gab(0, 1);
+        om2 = ox * ox + oy * oy + oz * oz;
+        rc_pin(om2);
+    }
+}
+
 // Whether the tile keeps unweighted D_y v and D_x u of the last three
 // leading planes in LDS, so that the nested cross differences D_x D_y v and
 // D_y D_x u read four values each instead of forming sixteen-point stencils:
@@ -397,9 +590,10 @@ __device__ __forceinline__ void finalize(const Acc<T>& A, const T cross[3], T rh
 // Not the 8-row tile, whose LDS must stay under half the CU's for two
 // workgroups, and not single precision, whose stage is bound by memory
 // (no gain measured, +2% on its monitored build).
-template <typename T, int TY, bool SS>
+// (Not in the recompute forms: they keep no derivative values.)
+template <typename T, int TY, bool SS, bool RC = false>
 constexpr bool d_ring() {
-    return !SS && sizeof(T) == 8 && TY == 16;
+    return !SS && !RC && sizeof(T) == 8 && TY == 16;
 }
 
 // Velocity ring slots. Five, or four where the fused tile keeps the D ring
@@ -407,9 +601,11 @@ constexpr bool d_ring() {
 // z-2, whose in-plane readers (it was the centre plane two barriers ago)
 // are done, and its own column, which the z fold still reads, is copied to
 // registers first.
-template <typename T, int TY, bool FUSED, bool SS>
+// The recompute forms read the velocity of all five planes with its
+// x-y halo (the z cross derivatives as nested stencils), so they keep five.
+template <typename T, int TY, bool FUSED, bool SS, bool RC = false>
 constexpr int ring_slots() {
-    return FUSED && d_ring<T, TY, SS>() ? 4 : 5;
+    return FUSED && d_ring<T, TY, SS, RC>() ? 4 : 5;
 }
 
 // Whether the fused form keeps a per-thread halo ring in LDS (each halo
@@ -452,7 +648,8 @@ struct PlaneLds {
 // parking plane z+2's in the same slot). With the D ring, sD holds
 // 3 * DSZ values. Ends with a barrier, so the caller may reuse the LDS for
 // another tile right away.
-template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false,
+          bool RC = false>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
                                             T* __restrict__ sV, T* __restrict__ sH,
                                             T* __restrict__ sD,
@@ -480,8 +677,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     constexpr bool kCentre = !SS && sizeof(T) == 8;
     using G = Geom<TX, TY>;
     constexpr int LX = G::LX, NPL = G::NPL, NT = G::NT, HPT = G::HPT, NHALO = G::NHALO;
-    constexpr int RING = ring_slots<T, TY, FUSED, SS>();
-    constexpr bool DR = d_ring<T, TY, SS>();
+    constexpr int RING = ring_slots<T, TY, FUSED, SS, RC>();
+    constexpr bool DR = d_ring<T, TY, SS, RC>();
     static_assert(!DR || G::DHALO <= G::NT, "the D-ring halo items need one thread each");
     static_assert(RING == 5 || (RING == 4 && FUSED), "four ring slots rely on the fused loop order");
     // velocity gradients of the centre plane that earlier work already holds
@@ -587,7 +784,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // (stored-gradient form: Xs and Xw queue the stored G_xx and G_yy of the
     // own column instead, for D_z of the diagonal gradients)
     T Xs[5], Xw[5], Yw[5];
-    if constexpr (SS) {
+    if constexpr (SS && !RC) {
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
             Xs[s] = A.grad[0 * n + poff(z0 - 2 + s) + col];
@@ -672,7 +869,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 V[2 * FOV + hidxV[h]] = w;
             }
         __syncthreads();
-        if constexpr (!SS) leading(V, Xs[s], Xw[s], Yw[s], zz, s >= 2);
+        if constexpr (!SS && !RC) leading(V, Xs[s], Xw[s], Yw[s], zz, s >= 2);
     }
 
     // prefetched halo values for the first iteration: fused form, raw q of
@@ -784,7 +981,26 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // the wrapped address of the tile's corner and is left unused, since a
         // branch here would make the wait for these loads also wait for this
         // plane's stores.
+        // The unfused double-precision recompute forms fetch after the
+        // compute instead: the prefetched stored primitives do not fit beside
+        // their residual (52-84 B of spills per lane against 19-36).
+        constexpr bool kLatePrefetch = RC && !FUSED && sizeof(T) == 8;
         Raw<T, FUSED> nxt;
+        auto fetch_next = [&]() {
+            load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+#pragma unroll
+            for (int h = 0; h < HPT; ++h)
+                if (hval[h]) {
+                    if constexpr (FUSED) {
+                        load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                        if constexpr (!HR)
+                            load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                    } else {
+                        load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                        load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                    }
+                }
+        };
         if constexpr (kLean) {
             const size_t z3 = poff(z + 3);
 #pragma unroll
@@ -802,26 +1018,14 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     for (int f = 0; f < 5; ++f)
                         hz[h].a[f] = plane_load<T>(plane_view(A.q + f * n + z1p, pq), hcolq[h]);
             }
-        } else {
-            load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+        } else if constexpr (!kLatePrefetch) {
+            fetch_next();
         }
         T gnx[SS ? 2 : 1];
-        if constexpr (SS) {
+        if constexpr (SS && !RC) {
             gnx[0] = A.grad[0 * n + poff(z + 3) + col];
             gnx[1] = A.grad[4 * n + poff(z + 3) + col];
         }
-#pragma unroll
-        for (int h = 0; h < HPT; ++h)
-            if (!kLean && hval[h]) {
-                if constexpr (FUSED) {
-                    load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
-                    if constexpr (!HR)
-                        load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
-                } else {
-                    load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
-                    load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
-                }
-            }
         // fused form: the accumulator of plane z. The lean single-precision
         // form fetches it here, before the compute, so its latency is
         // covered; in double precision the registers are not there (the spill
@@ -841,15 +1045,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         if constexpr (kHaloPrio) __builtin_amdgcn_s_setprio(0);
 
         // (c) leading-plane in-plane derivatives for the z cross terms
-        if constexpr (!SS) leading(Vl, Xs[4], Xw[4], Yw[4], z + 2, true);
+        if constexpr (!SS && !RC) leading(Vl, Xs[4], Xw[4], Yw[4], z + 2, true);
 
         // (d) residual at plane z
         const T* Vc = ring(z);
+        const T uc[3] = {Vc[ownV], Vc[FOV + ownV], Vc[2 * FOV + ownV]};
+        T R[5];
+        T om2 = T(0);
+        if constexpr (RC) {
+            recompute_point<T, SS, MON>(RcView<T>{Pz, {ring(z - 2), ring(z - 1), Vc, ring(z + 1), ring(z + 2)},
+                                                  ownP, ownV, FOP, RSP, FOV, RSV},
+                                        Qz, uc, k, A.grad, n, poff, z, col, xnb, ynb, R, om2);
+        } else {
         Acc<T> ac;
         ac.S0 = ac.SE = ac.HEAT = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) ac.Sm[a] = ac.LAP[a] = T(0);
-        const T uc[3] = {Vc[ownV], Vc[FOV + ownV], Vc[2 * FOV + ownV]};
         {  // x
             T rho[5], m[3][5], E[5], p[5], tt[5], vel[3][5];
 #pragma unroll
@@ -985,8 +1196,6 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             cross[1] = k.a1[1] * (k.a1[0] * dydxu + a1z * D1u(Yw[0], Yw[1], Yw[3], Yw[4]));
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], a1z, a2z);
         }
-        T R[5];
-        T om2;
         {
             T mc[3] = {Qz[2].m0, Qz[2].m1, Qz[2].m2};
             if constexpr (kMomFromVel)
@@ -994,6 +1203,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 for (int a = 0; a < 3; ++a) mc[a] = Qz[2].rho * uc[a];
             finalize<T, !SS, kCentre>(ac, cross, Qz[2].rho, mc, Qz[2].E, Qz[2].t, uc, k, R, om2);
         }
+        }  // thread-local form
+        if constexpr (kLatePrefetch) fetch_next();
         if constexpr (MON) {
             if (active) {
                 // kinetic energy and enstrophy of the input state (Section 3
@@ -1047,7 +1258,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 for (int f = 0; f < 5; ++f) stream_store(R[f], A.r + f * n + oidx);
             }
         }
-        if constexpr (PlaneLds<SS>::kBuffers == 1) __syncthreads();
+        // Second barrier: single-buffered plane fields (stored-gradient
+        // forms), and the recompute forms, whose nested z stencils read the
+        // neighbours' columns of ring plane z-2, the slot the next iteration
+        // overwrites with plane z+3 before its barrier.
+        if constexpr (PlaneLds<SS>::kBuffers == 1 || RC) __syncthreads();
         // (e) rotate the queues (double-buffered plane fields: no barrier, see kPF)
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -1057,7 +1272,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Yw[s] = Yw[s + 1];
         }
         Qz[4] = finish<T, FUSED>(nxt, k, unew);
-        if constexpr (SS) {
+        if constexpr (SS && !RC) {
             Xs[4] = gnx[0];
             Xw[4] = gnx[1];
         }
@@ -1129,22 +1344,23 @@ __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict_
 
 // Waves per SIMD the register budget is tuned for: double-precision tiles
 // need up to 256 VGPRs (two waves), single precision fits three.
-template <typename T>
+template <typename T, bool RC = false>
 struct Occ {
-    static constexpr int kWaves = sizeof(T) == 8 ? 2 : 3;
+    static constexpr int kWaves = (sizeof(T) == 8 || RC) ? 2 : 3;
 };
 
-template <typename T, int TX, int TY, bool FUSED, bool SS, bool MON>
+template <typename T, int TX, int TY, bool FUSED, bool SS, bool MON, bool RC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
-                               amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
+                               amdgpu_waves_per_eu(Occ<T, RC>::kWaves, Occ<T, RC>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
-    __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, FUSED, SS>() * 3 * G::NPL];
+    __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, FUSED, SS, RC>() * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 2 * kPF * G::NHALO : 1];
-    __shared__ T sD[d_ring<T, TY, SS>() ? 3 * G::DSZ : 1];
+    __shared__ T sD[d_ring<T, TY, SS, RC>() ? 3 * G::DSZ : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
-    zsweep_tile<T, TX, TY, FUSED, SS, MON>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sD, sM);
+    zsweep_tile<T, TX, TY, FUSED, SS, MON, RC>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sD,
+                                               sM);
 }
 
 // Persistent batched stage kernel: workgroup b runs its own run of the
@@ -1187,7 +1403,8 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
     }
 }
 
-template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false>
+template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false,
+          bool RC = false>
 void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     ZArgs<T> a = a0;
     const Dims& d = a.d;
@@ -1196,7 +1413,8 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     a.tiles_y = (d.ny + TY - 1) / TY;
     const int tiles_z = (d.nz + a.zchunk - 1) / a.zchunk;
     const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * tiles_z);
-    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS, MON>), dim3(nb), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS, MON, RC>), dim3(nb), dim3(TX * TY), 0, s,
+                       a);
 }
 
 }  // namespace
@@ -1220,22 +1438,27 @@ void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* t
 
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, int tile_y, hipStream_t s) {
-    TimerScope ts("ra_zsweep", s);
+                      int zchunk, int tile_y, hipStream_t s, bool recompute) {
+    TimerScope ts(recompute ? "ra_zsweep" : "sn_zsweep", s);
     ZArgs<T> a{};
     a.d = d;
     a.k = c;
     a.q = q;
     a.prim = prim;
     a.r = r;
-    if (tile_y == 16) launch_tiles<T, kTX, 16, false>(a, zchunk, s);
-    else launch_tiles<T, kTX, 8, false>(a, zchunk, s);
+    if (recompute) {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, false, false, true>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, false, false, true>(a, zchunk, s);
+    } else {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false>(a, zchunk, s);
+    }
 }
 
 template <typename T>
 void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
-                      T* r, int zchunk, int tile_y, hipStream_t s) {
-    TimerScope ts("ss_zsweep", s);
+                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute) {
+    TimerScope ts(recompute ? "rs_zsweep" : "ss_zsweep", s);
     ZArgs<T> a{};
     a.d = d;
     a.k = c;
@@ -1243,8 +1466,13 @@ void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.prim = prim;
     a.grad = grad;
     a.r = r;
-    if (tile_y == 16) launch_tiles<T, kTX, 16, false, true>(a, zchunk, s);
-    else launch_tiles<T, kTX, 8, false, true>(a, zchunk, s);
+    if (recompute) {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, true>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, true, false, true>(a, zchunk, s);
+    } else {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, true>(a, zchunk, s);
+    }
 }
 
 template <typename T>
@@ -1281,8 +1509,10 @@ int sweep_tiles(const Dims& d, int zchunk, int tile_y) {
 
 template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
-                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s, double* mpart) {
-    TimerScope ts(mpart ? "ra_fused_mon" : "ra_fused", s);
+                     const StageCoef& sc, int zchunk, int tile_y, hipStream_t s, double* mpart,
+                     bool recompute) {
+    TimerScope ts(recompute ? (mpart ? "ra_fused_mon" : "ra_fused")
+                            : (mpart ? "sn_fused_mon" : "sn_fused"), s);
     ZArgs<T> a{};
     a.mpart = mpart;
     a.d = d;
@@ -1293,7 +1523,15 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
-    if (mpart) {
+    if (recompute) {
+        if (mpart) {
+            if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, true, true>(a, zchunk, s);
+            else launch_tiles<T, kTX, 8, true, false, true, true>(a, zchunk, s);
+        } else {
+            if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, false, true>(a, zchunk, s);
+            else launch_tiles<T, kTX, 8, true, false, false, true>(a, zchunk, s);
+        }
+    } else if (mpart) {
         if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, true>(a, zchunk, s);
         else launch_tiles<T, kTX, 8, true, false, true>(a, zchunk, s);
     } else {
@@ -1307,11 +1545,11 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
                                      hipStream_t);                                            \
     template int batch_blocks_per_cu<T>(int);                                                 \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
-                                      int, int, hipStream_t);                               \
+                                      int, int, hipStream_t, bool);                         \
     template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
-                                      const T*, T*, int, int, hipStream_t);                 \
+                                      const T*, T*, int, int, hipStream_t, bool);           \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
-                                     const StageCoef&, int, int, hipStream_t, double*);
+                                     const StageCoef&, int, int, hipStream_t, double*, bool);
 NSF_INST(float)
 NSF_INST(double)
 #undef NSF_INST

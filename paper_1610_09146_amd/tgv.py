@@ -25,7 +25,7 @@ import torch
 from . import nsf, workloads as W
 
 
-def run(n: int, t_end: float, precision: str = "f64", variant="RA", tune: dict | None = None,
+def run(n: int, t_end: float, precision: str = "f64", variant="SN", tune: dict | None = None,
         phys: dict | None = None, tgv: dict | None = None, chunk: int = 2000,
         log=None) -> dict:
     """Evolve the n^3 Taylor-Green vortex to t_end; returns the record
@@ -84,7 +84,7 @@ def main(argv=None) -> int:
     ap.add_argument("--n", type=int, nargs="+", default=[64])
     ap.add_argument("--t-end", type=float, default=20.0)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--variant", default="RA")
+    ap.add_argument("--variant", default="SN")
     ap.add_argument("--every", type=int, default=10, help="keep every k-th sample in the output")
     ap.add_argument("--out", default=None, help="JSON file for the records")
     args = ap.parse_args(argv)

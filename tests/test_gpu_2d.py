@@ -25,8 +25,9 @@ from paper_1610_09146_amd import nsf  # noqa: E402
 
 PHYS = W.TGV_PHYS
 SHAPES = [(48, 40, 1), (37, 21, 1), (70, 11, 1)]
-CASES = [("BL", None), ("RA", None), ("SS", None), ("RA", {"naive": 1}), ("SS", {"naive": 1}),
-         ("RA", {"block_y": 8}), ("RA", {"block_y": 16})]
+CASES = [("BL", None), ("RA", None), ("SS", None), ("SN", None), ("RS", None), ("RA", {"naive": 1}),
+         ("SS", {"naive": 1}), ("RA", {"block_y": 8}), ("RA", {"block_y": 16}),
+         ("SN", {"block_y": 8}), ("SN", {"block_y": 16})]
 
 
 def state2d(shape, seed=3):

@@ -27,7 +27,7 @@ def small_instances(count=6, seed=5):
 
 
 def single(inst, precision, nsteps):
-    s = nsf.Solver(inst["shape"], inst["phys"], "RA", precision, tune={"fuse": 1})
+    s = nsf.Solver(inst["shape"], inst["phys"], "SN", precision, tune={"fuse": 1})
     s.init(inst["tgv"])
     s.step(inst["dt"], nsteps)
     return s

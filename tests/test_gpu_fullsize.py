@@ -1,10 +1,11 @@
 """GPU: the timed workloads at full size, in the launch configurations the
 benchmark times: 512^3 Taylor-Green (pointwise +-1e-3 perturbation, seed
-1610, dt = 4.23125e-4), one monitored RK step of the fused RA form, in
+1610, dt = 4.23125e-4), one monitored RK step of the fused SN form, in
 double precision with 32 x 16 tiles and in the single-precision form with
 32 x 8 tiles, 64-plane z-chunks (Section 2 time loop, Section 3 set-up);
 and at 256^3 (dt = 8.4625e-4) the monitored step of each algorithm the
-benchmark compares there (BL, SS, RA with stored primitives).
+benchmark compares there (BL, RA, RS, SN, SS with stored primitives, and
+the fused RA).
 
 The oracle cannot advance 2^27 points in seconds, but a step's result on a
 few z-planes depends only on six planes either side of them, so sampled
@@ -45,7 +46,7 @@ def _planes(t, k0, k1):
 
 def test_512_monitored_fused_step_sampled_planes():
     print(f"case fullsize fused monitored step {N} {TUNE}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "RA", "f64", tune=TUNE)
+    s = nsf.Solver((N, N, N), PHYS, "SN", "f64", tune=TUNE)
     s.init(W.tgv_pointwise(1610))
     dt = W.tgv_dt(N)
     slabs = {k0: _planes(s.q, k0 - 6, k1 + 6) for k0, k1 in SAMPLES}
@@ -71,7 +72,7 @@ def test_512_monitored_fused_step_sampled_planes():
 def test_512_monitored_fused_step_f32_form_sampled_planes():
     tune = {"fuse": 1, "block_y": 8, "zchunk": 64}
     print(f"case fullsize fused monitored step f32 {N} {tune}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "RA", "f32", tune=tune)
+    s = nsf.Solver((N, N, N), PHYS, "SN", "f32", tune=tune)
     s.init(W.tgv_pointwise(1610))
     dt = W.tgv_dt(N)
     slabs = {k0: _planes(s.q_acc, k0 - 6, k1 + 6) for k0, k1 in SAMPLES}
@@ -94,13 +95,14 @@ def test_512_monitored_fused_step_f32_form_sampled_planes():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("variant", ["BL", "SS", "RA"])
-def test_256_monitored_step_sampled_planes(variant):
+@pytest.mark.parametrize("variant,tune", [("BL", None), ("SS", None), ("RA", None), ("RS", None),
+                                          ("SN", None), ("RA", {"fuse": 1})])
+def test_256_monitored_step_sampled_planes(variant, tune):
     # the 256^3 comparison of the algorithms (pointwise +-1e-3, seed 1610,
     # dt = 8.4625e-4): each variant's monitored step at its default tuning
     n = 256
-    print(f"case fullsize monitored step {variant} {n}", flush=True)
-    s = nsf.Solver((n, n, n), PHYS, variant, "f64")
+    print(f"case fullsize monitored step {variant} {tune} {n}", flush=True)
+    s = nsf.Solver((n, n, n), PHYS, variant, "f64", tune=tune)
     s.init(W.tgv_pointwise(1610))
     dt = W.tgv_dt(n)
     samples = [(0, 2), (n // 2 - 1, n // 2 + 1), (n - 2, n)]

@@ -30,7 +30,7 @@ TUNE = {"fuse": 1}
 def _room():
     torch.cuda.empty_cache()
     free, _ = torch.cuda.mem_get_info()
-    need = nsf.workspace_bytes((N, N, N), "RA", "f64", TUNE) + 3 * 5 * N ** 3 * 8
+    need = nsf.workspace_bytes((N, N, N), "SN", "f64", TUNE) + 3 * 5 * N ** 3 * 8
     if free < need + (2 << 30):
         pytest.skip(f"needs {need / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
 
@@ -38,7 +38,7 @@ def _room():
 def test_1024_rhs_sampled_planes():
     _room()
     print(f"case large RA fused {N}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "RA", "f64", tune=TUNE)
+    s = nsf.Solver((N, N, N), PHYS, "SN", "f64", tune=TUNE)
     s.init(W.tgv_pointwise(1610))
     s.rhs()
     torch.cuda.synchronize()
@@ -57,7 +57,7 @@ def test_1024_rhs_sampled_planes():
 def test_1024_monitored_step_closed_forms():
     _room()
     print(f"case large monitored step {N}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "RA", "f64", tune=TUNE)
+    s = nsf.Solver((N, N, N), PHYS, "SN", "f64", tune=TUNE)
     s.init(W.tgv_unperturbed())
     dt = W.tgv_dt(N)
     mon = torch.zeros(4, dtype=torch.float64, device="cuda")

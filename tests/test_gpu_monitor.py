@@ -2,8 +2,8 @@
 
 nsf_rk_step_monitored records, per step, the grid means of rho|u|^2/2 and
 rho|curl u|^2/2 (Section 3 diagnostics) of the state at the start of the
-step. The fused RA form takes these sums inside its first stage kernel, the
-other forms run the diagnostics pass. Checked against the oracle's
+step. The fused SN and RA forms take these sums inside their first stage
+kernel, the other forms run the diagnostics pass. Checked against the oracle's
 diagnostics of the oracle's own RK trajectory (extended precision) and
 against nsf_diagnostics of the same GPU states, and the monitored run must
 leave the same state as the unmonitored one.
@@ -41,14 +41,20 @@ NSTEPS = 3
 TGV = W.tgv_pointwise(5, 1e-3)
 
 CASES = [
+    ("SN", "f64", {"fuse": 1}),
+    ("SN", "f64", {"fuse": 1, "block_y": 8, "zchunk": 7}),
+    ("SN", "f32", {"fuse": 1}),
+    ("SN", "f32", {"fuse": 1, "block_y": 16, "zchunk": 5}),
     ("RA", "f64", {"fuse": 1}),
     ("RA", "f64", {"fuse": 1, "block_y": 8, "zchunk": 7}),
-    ("RA", "f32", {"fuse": 1}),
     ("RA", "f32", {"fuse": 1, "block_y": 16, "zchunk": 5}),
     ("RA", "f64", None),
+    ("SN", "f64", None),
     ("SS", "f64", None),
+    ("RS", "f64", None),
     ("BL", "f64", None),
     ("SS", "f32", None),
+    ("RS", "f32", None),
 ]
 
 
@@ -121,13 +127,13 @@ def test_monitor_deterministic_and_zero_steps():
     dt = W.tgv_dt(max(SHAPE))
     runs = []
     for _ in range(2):
-        s = _solver("RA", "f64", {"fuse": 1})
+        s = _solver("SN", "f64", {"fuse": 1})
         mon = torch.zeros(2 * NSTEPS, dtype=torch.float64, device="cuda")
         s.step_monitored(dt, NSTEPS, mon)
         runs.append(mon.cpu())
     assert torch.equal(runs[0], runs[1])
     # nsteps = 0 writes nothing and leaves the state alone
-    s = _solver("RA", "f64", {"fuse": 1})
+    s = _solver("SN", "f64", {"fuse": 1})
     before = s.q.clone()
     mon = torch.full((2,), 7.0, dtype=torch.float64, device="cuda")
     s.step_monitored(dt, 0, mon)
@@ -142,8 +148,9 @@ def test_monitor_tgv_closed_forms():
     n = 64
     # float: the initial state is rounded to float and the fused kernel forms
     # u and curl u in float (about 2e-6 relative, see the bars above)
-    for precision, tol in (("f64", 1e-13), ("f32", 1e-5)):
-        s = nsf.Solver((n, n, n), PHYS, "RA", precision, tune={"fuse": 1})
+    for variant, precision, tol in (("SN", "f64", 1e-13), ("SN", "f32", 1e-5), ("RA", "f64", 1e-13),
+                                    ("RA", "f32", 1e-5)):
+        s = nsf.Solver((n, n, n), PHYS, variant, precision, tune={"fuse": 1})
         s.init(W.tgv_unperturbed())
         mon = torch.zeros(2, dtype=torch.float64, device="cuda")
         s.step_monitored(W.tgv_dt(n), 1, mon)

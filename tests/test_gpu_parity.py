@@ -24,7 +24,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 from paper_1610_09146_amd import nsf  # noqa: E402
 
 PHYS = W.TGV_PHYS
-VARIANTS = ["BL", "RA", "SS"]
+VARIANTS = ["BL", "RA", "SS", "SN", "RS"]
 SHAPES = [(8, 8, 8), (16, 16, 16), (32, 32, 32), (70, 11, 7), (40, 36, 50), (5, 6, 7)]
 
 
@@ -196,8 +196,8 @@ def f32_bar(q_ld, ref_ld):
 def test_rhs_f32_form(variant, tune):
     # FP32 fields and arithmetic against the extended-precision oracle on the
     # same (FP32-rounded) input
-    if tune and variant != "RA":
-        pytest.skip("tuning applies to RA")
+    if tune and variant == "BL":
+        pytest.skip("BL has no untiled form: its derivative loops are the per-point kernels")
     shape = (32, 32, 32)
     q = perturbed_state(shape)
     q32 = q.astype(np.float32)
@@ -208,7 +208,8 @@ def test_rhs_f32_form(variant, tune):
     assert np.all(err <= bar), (err, bar)
 
 
-@pytest.mark.parametrize("n,variant", [(256, "RA"), (256, "SS"), (256, "BL"), (512, "RA")])
+@pytest.mark.parametrize("n,variant", [(256, "RA"), (256, "SS"), (256, "BL"), (256, "RS"),
+                                       (256, "SN"), (512, "SN")])
 def test_rhs_large_sampled_planes(n, variant):
     # full-size grids: GPU residual on the whole grid, oracle on sampled
     # z-slabs (planes near the periodic seam and in the interior)
@@ -236,23 +237,25 @@ def test_rhs_large_sampled_planes(n, variant):
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("tune", [{"naive": 1}, {"zchunk": 7}, {"zchunk": 3},
                                   {"block_y": 8}, {"block_y": 16, "zchunk": 9}])
-def test_rhs_f64_parity_ra_tunings(shape, tune):
-    print(f"case rhs_ra_tune {tune} {shape}", flush=True)
+@pytest.mark.parametrize("variant", ["RA", "SN"])
+def test_rhs_f64_parity_ra_tunings(shape, tune, variant):
+    print(f"case rhs_tune {variant} {tune} {shape}", flush=True)
     q = perturbed_state(shape)
     ref = O.rhs(q, PHYS, prec="ld")
-    got = gpu_rhs(shape, "RA", "f64", q.astype(np.float64), tune=tune)
+    got = gpu_rhs(shape, variant, "f64", q.astype(np.float64), tune=tune)
     err = rel_err(got, ref)
     bar = f64_bar(shape, q, ref)
     assert np.all(err <= bar), (err, bar)
 
 
 @pytest.mark.parametrize("zchunk", [0, 5])
-def test_rk_fused_ten_steps_tgv32(zchunk):
+@pytest.mark.parametrize("variant", ["RA", "SN"])
+def test_rk_fused_ten_steps_tgv32(zchunk, variant):
     shape, n = (32, 32, 32), 32
     dt = W.tgv_dt(n)
     q0 = O.init(shape, PHYS, W.tgv_unperturbed(), prec="ld")
     ref = O.rk_step(q0, PHYS, dt, 10, prec="ld")
-    s = nsf.Solver(shape, PHYS, "RA", "f64", tune={"fuse": 1, "zchunk": zchunk})
+    s = nsf.Solver(shape, PHYS, variant, "f64", tune={"fuse": 1, "zchunk": zchunk})
     s.init(W.tgv_unperturbed())
     s.step(dt, 10)
     err = rel_err(s.q.cpu().numpy(), ref)
@@ -263,18 +266,19 @@ def test_rk_fused_ten_steps_tgv32(zchunk):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 50), (5, 6, 7), (70, 11, 9)])
 @pytest.mark.parametrize("block_y", [8, 16])
-def test_rk_fused_matches_unfused(precision, shape, block_y):
+@pytest.mark.parametrize("variant", ["RA", "SN"])
+def test_rk_fused_matches_unfused(precision, shape, block_y, variant):
     # the fused stage kernel (primitives recomputed in the tile, update in
     # the epilogue) agrees with the stored-primitive path to round-off: to
     # 1e-13 (FP64) or 1e-5 (FP32), or within 4x the stored-primitive path's
     # own error against the extended-precision oracle, per field. The two
     # builds may fuse multiply-adds differently, and rho w (small next to
     # the other momenta) has the largest relative rounding error.
-    print(f"case fused_vs_unfused {precision} {shape} {block_y}", flush=True)
+    print(f"case fused_vs_unfused {variant} {precision} {shape} {block_y}", flush=True)
     tgv = W.tgv_pointwise(17, 1e-2)
     out = {}
     for name, tune in (("plain", {"block_y": 8}), ("fused", {"fuse": 1, "block_y": block_y})):
-        s = nsf.Solver(shape, PHYS, "RA", precision, tune=tune)
+        s = nsf.Solver(shape, PHYS, variant, precision, tune=tune)
         s.init(tgv)
         s.step(2e-3, 3)
         out[name] = (s.q.cpu().numpy().astype(np.float64), s.q_acc.cpu().numpy())
@@ -294,8 +298,9 @@ def test_rk_f32_form_against_f64_oracle():
     q0 = O.init(shape, PHYS, W.tgv_unperturbed(), prec="d")
     ref = O.rk_step(q0, PHYS, dt, 10, prec="d")
     ref_d = O.diagnostics(ref, PHYS)
-    for tune in (None, {"fuse": 1}):
-        s = nsf.Solver(shape, PHYS, "RA", "f32", tune=tune)
+    for variant, tune in (("SN", None), ("SN", {"fuse": 1}), ("RA", None), ("RA", {"fuse": 1}),
+                          ("RS", None)):
+        s = nsf.Solver(shape, PHYS, variant, "f32", tune=tune)
         s.init(W.tgv_unperturbed())
         s.step(dt, 10)
         err = rel_err(s.q_acc.cpu().numpy(), ref)

@@ -1,4 +1,4 @@
-"""Autotuner and the SN / RS algorithm entries on the GPU."""
+"""Autotuner, and the RA / SN / RS algorithms as kernels of their own, on the GPU."""
 import os
 
 import numpy as np
@@ -40,17 +40,59 @@ def test_autotune_choice_is_parity_gated_and_used_by_auto(tmp_path, precision):
     assert torch.equal(a.q, b.q) and torch.equal(a.q_acc, b.q_acc)
 
 
-@pytest.mark.parametrize("variant", ["SN", "RS"])
-@pytest.mark.parametrize("shape", [(16, 16, 16), (40, 36, 50)])
-def test_sn_rs_parity(variant, shape):
+FAMILIES = ("ra_zsweep", "sn_zsweep", "ss_zsweep", "rs_zsweep", "ra_fused", "sn_fused")
+
+
+@pytest.mark.parametrize("variant,tune,family", [
+    ("RA", None, "ra_zsweep"), ("SN", None, "sn_zsweep"), ("SS", None, "ss_zsweep"),
+    ("RS", None, "rs_zsweep"), ("RA", {"fuse": 1}, "ra_fused"), ("SN", {"fuse": 1}, "sn_fused")])
+def test_each_algorithm_runs_its_own_kernel(variant, tune, family):
+    # RA, SN, RS and SS are separate kernels: one RK step of each launches
+    # its own kernel family three times and none of the others'
+    shape = (40, 36, 50)
+    s = nsf.Solver(shape, PHYS, variant, "f64", tune=tune)
+    s.init(W.tgv_pointwise(3, 1e-3))
+    for fam in FAMILIES:
+        nsf.timer_enable(fam)
+        s.step(1e-3, 1)
+        torch.cuda.synchronize()
+        count, _ = nsf.timer_read()
+        nsf.timer_enable(None)
+        assert count == (3 if fam == family else 0), (fam, count)
+
+
+@pytest.mark.parametrize("variant", ["SN", "RS", "RA"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (40, 36, 50), (70, 11, 9), (5, 6, 7)])
+@pytest.mark.parametrize("tune", [None, {"block_y": 16, "zchunk": 5}, {"block_y": 8, "zchunk": 7}])
+def test_sn_rs_ra_parity(variant, shape, tune):
+    print(f"case parity {variant} {shape} {tune}", flush=True)
     q = O.init(shape, PHYS, W.tgv_pointwise(3, 1e-3), prec="ld")
     ref = O.rhs(q, PHYS, prec="ld")
-    s = nsf.Solver(shape, PHYS, variant, "f64")
+    s = nsf.Solver(shape, PHYS, variant, "f64", tune=tune)
     s.q.copy_(torch.from_numpy(q.astype(np.float64)))
     s.rhs()
     err = rel_err(s.r.cpu().numpy(), ref)
     floor = rel_err(O.rhs(q.astype(np.float64), PHYS, prec="d"), ref)
     assert np.all(err <= np.maximum(1e-12, 4 * floor)), err
+
+
+def test_recompute_and_thread_local_forms_round_differently():
+    # RA and SN (and RS and SS) form the same derivatives in different
+    # orders, so their residuals agree to round-off but not bit for bit
+    shape = (40, 36, 50)
+    q = O.init(shape, PHYS, W.tgv_pointwise(3, 1e-3), prec="d")
+    out = {}
+    for v in ("RA", "SN", "RS", "SS"):
+        s = nsf.Solver(shape, PHYS, v, "f64")
+        s.q.copy_(torch.from_numpy(q))
+        s.rhs()
+        out[v] = s.r.clone()
+    assert not torch.equal(out["RA"], out["SN"])
+    assert not torch.equal(out["RS"], out["SS"])
+    ref = O.rhs(q.astype(np.longdouble), PHYS, prec="ld")
+    bar = np.maximum(1e-12, 8 * rel_err(O.rhs(q, PHYS, prec="d"), ref))
+    assert np.all(rel_err(out["RA"].cpu().numpy(), out["SN"].cpu().numpy()) <= bar)
+    assert np.all(rel_err(out["RS"].cpu().numpy(), out["SS"].cpu().numpy()) <= bar)
 
 
 @pytest.mark.parametrize("tune", [None, {"naive": 1}, {"zchunk": 7, "block_y": 8},
