@@ -40,10 +40,18 @@ FAMILY_BYTES = {
     "ra_naive": (120, 60),        # q, prims -> r (untiled, RA and SN)
     "ra_zsweep": (120, 60),       # RA: q, prims -> r
     "sn_zsweep": (120, 60),       # SN: q, prims -> r
+    # fused stages. Double precision: the first substep reads the
+    # accumulator from q (equal at a step boundary): q -> q_next, q_acc; a
+    # third substep other than a call's last leaves q_acc unwritten:
+    # q, q_acc -> q_next
     "ra_fused": (160, 120),       # RA: q, q_acc -> q_next, q_acc
-    "ra_fused_mon": (160, 120),   # the same, plus per-tile KE / enstrophy sums
+    "ra_fused_mon": (120, 120),   # RA first substep, plus per-tile KE / enstrophy sums
+    "ra_fused_first": (120, 120),  # RA first substep, unmonitored
+    "ra_fused_last": (120, 120),  # RA third substep without the q_acc store
     "sn_fused": (160, 120),       # SN: q, q_acc -> q_next, q_acc
-    "sn_fused_mon": (160, 120),   # the same, plus per-tile KE / enstrophy sums
+    "sn_fused_mon": (120, 120),   # SN first substep, plus per-tile KE / enstrophy sums
+    "sn_fused_first": (120, 120),  # SN first substep, unmonitored
+    "sn_fused_last": (120, 120),  # SN third substep without the q_acc store
     "rs_zsweep": (192, 96),       # RS: q, prims, 9 gradients -> r
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
@@ -95,7 +103,7 @@ def families(variant, tune):
     if variant in ("RA", "SN"):
         k = variant.lower()
         if tune and tune.get("fuse"):
-            return [f"{k}_fused", f"{k}_fused_mon"]
+            return [f"{k}_fused", f"{k}_fused_mon", f"{k}_fused_last"]
         if tune and tune.get("naive"):
             return ["prims", "ra_naive", "update", "diag"]
         return ["prims", f"{k}_zsweep", "update", "diag"]
@@ -120,19 +128,21 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_famili
     s.init(tgv or W.tgv_unperturbed())
     mon = torch.zeros(2 * max(steps, 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
-    # warmup; also find the family with the largest summed kernel time
-    fam_ms = {}
+    # warmup; also find the family with the largest summed kernel time, in
+    # untimed calls of the same form as the timed one (a few steps each)
+    fam_ms, fam_n = {}, {}
     fams = families(variant, tune)
     for w in range(max(warmup, 1)):
         s.step_monitored(dt, 1, mon)
     s.diagnostics()  # raises on non-finite values
     if time_families:
+        k = min(steps, 5)
         for fam in fams:
             nsf.timer_enable(fam)
-            s.step_monitored(dt, 1, mon)
+            s.step_monitored(dt, k, mon)
             torch.cuda.synchronize()
             c, ms = nsf.timer_read()
-            fam_ms[fam] = ms
+            fam_ms[fam], fam_n[fam] = ms / k, c / k
         nsf.timer_enable(None)
     dominant = max(fam_ms, key=fam_ms.get) if fam_ms else None
     # per-launch time of the dominant family (roofline): HIP events around
@@ -158,7 +168,7 @@ def run_variant(nsf, torch, W, n, variant, precision, steps, warmup, time_famili
         "variant": variant, "precision": precision, "n": n, "steps": steps, "tune": tune,
         "ms_per_step": ms_per_step, "pt_rhs_per_s": rate, "dominant": dominant,
         "dominant_launches": kcount, "dominant_ms_total": kms,
-        "family_ms_one_step": fam_ms,
+        "family_ms_one_step": fam_ms, "family_launches_one_step": fam_n,
         "ke": float(diag[0]),
         "enstrophy": float(diag[1]),
         "monitor_first": [float(x) for x in monitor[0]],
@@ -301,6 +311,20 @@ def copy_peak(nsf, torch, gib=4, reps=5):
     torch.cuda.empty_cache()
     return {"GBps": round(2 * n * 8 / best / 1e6, 1), "ms": round(best, 4),
             "kernel": f"k_copy16 (nsf_device_copy), {gib} GiB read + {gib} GiB written, best of {reps}"}
+
+
+def stage_roofline(res, precision):
+    """Algorithmic bytes over kernel time of all the kernels of one step
+    (every timed family), per step: the whole step's HBM roofline."""
+    col = 0 if precision == "f64" else 1
+    ms = sum(res["family_ms_one_step"].values())
+    if not ms:
+        return None
+    byts = sum(FAMILY_BYTES[f][col] * res["family_launches_one_step"][f] * res["n"] ** 3
+               for f in res["family_ms_one_step"])
+    return {"algorithmic_bytes_per_step": byts, "kernel_ms_per_step": round(ms, 4),
+            "achieved_GBps": round(byts / ms / 1e6, 1),
+            "frac": round(byts / ms / 1e6 / HBM_PEAK_GBS, 4)}
 
 
 def roofline_of(res, precision):
@@ -470,9 +494,11 @@ def main() -> int:
                 r = run_variant(nsf, torch, W, nt, v, "f64", 100, 1, tune=tune,
                                 tgv=W.tgv_pointwise(1610, 1e-3))
                 rl = roofline_of(r, "f64")
+                sr = stage_roofline(r, "f64")
                 table.append({"n": nt, "algorithm": name, "ms_per_step": round(r["ms_per_step"], 4),
                               "pt_rhs_per_s": r["pt_rhs_per_s"], "dominant": r["dominant"],
                               "dominant_frac_of_8TBs": rl["frac"] if rl else None,
+                              "step_frac_of_8TBs": sr["frac"] if sr else None,
                               "family_ms_one_step": r["family_ms_one_step"]})
         extras["table1_f64"] = table
         # the largest single-GPU grid, 1024^3 (about 215 GB), when it fits
@@ -510,6 +536,7 @@ def main() -> int:
         "autotune": tuned,
         "copy_peak": COPY_PEAK,
         "roofline": roofline_of(main_res, args.precision),
+        "step_roofline": stage_roofline(main_res, args.precision),
         "main": main_res,
         "extras": extras,
     }

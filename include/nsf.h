@@ -162,8 +162,11 @@ int nsf_rhs(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
  *   r = R(q); q = q_acc + A_s dt r (s < 3); q_acc = q_acc + B_s dt r;
  * then q = q_acc; A = (2/3, 5/12), B = (1/4, 3/20, 3/5).
  * On entry q_acc must hold the state (double) and q its value in the
- * precision dtype; on return both hold the new state. r is a 5-field
- * scratch in the precision dtype. Asynchronous. */
+ * precision dtype; on return both hold the new state. (In double precision
+ * the two are then equal, and the fused form uses that: its first substep
+ * reads the accumulator from q, and its third substep writes q_acc only in
+ * the call's last step.) r is a 5-field scratch in the precision dtype.
+ * Asynchronous. */
 int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
                 const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
                 double *q_acc, void *r, void *work, size_t work_bytes, void *stream);

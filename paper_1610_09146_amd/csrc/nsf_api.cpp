@@ -324,6 +324,14 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.a_dt = st < 2 ? A[st] * dt : 0.0;
                 sc.b_dt = B[st] * dt;
                 sc.last = st == 2;
+                // double precision: the state and the accumulator are equal at
+                // a step boundary, so the first substep reads the accumulator
+                // from q, and only the call's last step stores q_acc in its
+                // third substep (the next step reads the state from q)
+                if (sizeof(T) == 8) {
+                    sc.acc_from_q = st == 0;
+                    sc.store_acc = st < 2 || step == nsteps - 1;
+                }
                 const bool mon = monitor && st == 0;
                 launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s,
                                    mon ? mpart : nullptr, variant == NSF_RA);
@@ -552,8 +560,8 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ra_fused_mon,"
-    "sn_zsweep,sn_fused,sn_fused_mon,ss_grad_naive,ss_naive,ss_grad,ss_zsweep,rs_zsweep,diag,copy,"
-    "ra_batch,batch_step";
+    "ra_fused_first,ra_fused_last,sn_zsweep,sn_fused,sn_fused_mon,sn_fused_first,sn_fused_last,"
+    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,rs_zsweep,diag,copy,ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

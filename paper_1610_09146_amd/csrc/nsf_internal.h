@@ -21,6 +21,12 @@ struct StageCoef {
     double a_dt;  // A_s dt (unused on the last substep)
     double b_dt;  // B_s dt
     int last;     // 1 on the third substep: q = q_acc after the update
+    // Double-precision fused stages only: the first substep reads the
+    // accumulator from the state q (equal to q_acc at a step boundary), and a
+    // third substep other than the call's last leaves q_acc unwritten (its
+    // value is the state the next step's first substep reads from q).
+    int acc_from_q = 0;
+    int store_acc = 1;
 };
 
 // Record an error message for nsf_last_error() and return `code`.
@@ -85,6 +91,8 @@ struct ZArgs {
     T* r;
     T* qout;
     double* qacc;
+    const double* qacc_in;  // where the fused stage reads the accumulator (qacc, or q)
+    int acc_store;          // fused stage: 0 leaves q_acc unwritten
     double a_dt, b_dt;
     int last;
     int zchunk, tiles_x, tiles_y;

@@ -896,6 +896,22 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // (three waves per SIMD) has no room for two more doubles.
     constexpr bool kLdsMon = MON && sizeof(T) == 4;
     double mke = 0.0, mens = 0.0;
+    // Lean double-precision 16-row form: the accumulator of plane z+1 is fetched
+    // right after plane z's stores, a whole plane of work ahead of its use
+    // (-2.8% on the 512^3 stage against fetching it in the epilogue, A/B on
+    // one box). Single precision fetches it early in the same iteration
+    // instead (kEarlyAcc; one plane ahead was neutral there); the 8-row
+    // double-precision tile has no registers for it. This form alone also
+    // takes the accumulator-saving substeps (ZArgs::qacc_in, acc_store).
+    constexpr bool kAccAhead = kLean && sizeof(T) == 8 && TY == 16;
+    double accN[kAccAhead ? 5 : 1];
+    if constexpr (kAccAhead) {
+        const uint32_t pb0 = (uint32_t)(plane * sizeof(double));
+        const uint32_t off0 = (active && z0 < z1) ? (uint32_t)col * 8u : kOutside;
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+            accN[f] = view_load(plane_view(A.qacc_in + f * n + (size_t)z0 * plane, pb0), off0);
+    }
     if constexpr (kLdsMon) sM[tid] = make_double2(0.0, 0.0);
 
     for (int z = z0; z < z1; ++z) {
@@ -1028,9 +1044,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         }
         // fused form: the accumulator of plane z. The lean single-precision
         // form fetches it here, before the compute, so its latency is
-        // covered; in double precision the registers are not there (the spill
-        // costs more than the exposed latency) and the monitored stage keeps
-        // its registers for the sums, so both fetch it in the epilogue.
+        // covered (the lean double-precision form has it from the previous
+        // iteration); the other fused forms fetch it in the epilogue.
         constexpr bool kEarlyAcc = kLean && sizeof(T) == 4;
         const size_t oidx = (size_t)z * plane + col;
         const size_t zo = (size_t)z * plane;
@@ -1227,17 +1242,29 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         if constexpr (kLean) {
             const uint32_t pbT = (uint32_t)(plane * sizeof(T));
             const uint32_t offT = active ? (uint32_t)(col * sizeof(T)) : kOutside;
-            if constexpr (!kEarlyAcc) {
+            if constexpr (kAccAhead) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) acc[f] = accN[f];
+            } else if constexpr (!kEarlyAcc) {
 #pragma unroll
                 for (int f = 0; f < 5; ++f) acc[f] = view_load(plane_view(A.qacc + f * n + zo, pb), off);
             }
             // the last stage's output is q_acc itself: the same fma with B dt
             const double out_dt = A.last ? A.b_dt : A.a_dt;
+            // (a third substep that leaves q_acc alone drops its stores by
+            // the out-of-range offset, without a branch)
+            const uint32_t offA = A.acc_store ? off : kOutside;
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
                 const double rr = (double)R[f];
-                view_store(fma(A.b_dt, rr, acc[f]), plane_view(A.qacc + f * n + zo, pb), off);
+                view_store(fma(A.b_dt, rr, acc[f]), plane_view(A.qacc + f * n + zo, pb), offA);
                 view_store((T)fma(out_dt, rr, acc[f]), plane_view(A.qout + f * n + zo, pbT), offT);
+            }
+            if constexpr (kAccAhead) {
+                const uint32_t offN = (active && z + 1 < z1) ? (uint32_t)col * 8u : kOutside;
+                const size_t zn = (size_t)(z + 1) * plane;
+#pragma unroll
+                for (int f = 0; f < 5; ++f) accN[f] = view_load(plane_view(A.qacc_in + f * n + zn, pb), offN);
             }
         } else if (active) {
             if constexpr (FUSED) {
@@ -1392,6 +1419,8 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.grad = nullptr;
         A.r = nullptr;
         A.qacc = bd.qacc;
+        A.qacc_in = bd.qacc;
+        A.acc_store = 1;
         A.a_dt = stage < 2 ? A_[stage] * bd.dt : 0.0;
         A.b_dt = B_[stage] * bd.dt;
         A.last = stage == 2;
@@ -1511,8 +1540,21 @@ template <typename T>
 void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, double* qacc,
                      const StageCoef& sc, int zchunk, int tile_y, hipStream_t s, double* mpart,
                      bool recompute) {
-    TimerScope ts(recompute ? (mpart ? "ra_fused_mon" : "ra_fused")
-                            : (mpart ? "sn_fused_mon" : "sn_fused"), s);
+    // The accumulator-saving substeps (first reads the accumulator from q,
+    // third leaves q_acc unwritten) in the double-precision 16-row form only;
+    // elsewhere every substep reads and writes q_acc (same results: q_acc
+    // equals q at a step boundary, and the value stored is the new state).
+    const bool saving = sizeof(T) == 8 && tile_y == 16;
+    const bool first_q = saving && sc.acc_from_q;
+    const bool last_ns = saving && !sc.store_acc;
+    // timer families by what a launch moves: the monitored first substep,
+    // an unmonitored first substep that reads the accumulator from q, a
+    // third substep that leaves q_acc unwritten, and the full stage
+    const char* fam = mpart ? (recompute ? "ra_fused_mon" : "sn_fused_mon")
+                      : first_q ? (recompute ? "ra_fused_first" : "sn_fused_first")
+                      : last_ns ? (recompute ? "ra_fused_last" : "sn_fused_last")
+                                : (recompute ? "ra_fused" : "sn_fused");
+    TimerScope ts(fam, s);
     ZArgs<T> a{};
     a.mpart = mpart;
     a.d = d;
@@ -1520,6 +1562,10 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.q = q;
     a.qout = qout;
     a.qacc = qacc;
+    // the first substep may read the accumulator from the state (double
+    // precision only: there q_acc equals q at a step boundary)
+    a.qacc_in = first_q ? reinterpret_cast<const double*>(q) : qacc;
+    a.acc_store = last_ns ? 0 : 1;
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
