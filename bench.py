@@ -183,7 +183,10 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     """64 uneven Taylor-Green instances, each step one graph replay (three
     persistent stage launches)."""
     insts = W.batch_instances()
-    b = nsf.Batch(insts, precision)
+    # the batched form's own autotuner: stage algorithm (SN / RA), tile
+    # height and z-chunk, searched on the ensemble
+    pick = nsf.batch_autotune(insts, precision, steps=3)
+    b = nsf.Batch(insts, precision, variant=pick["variant"], tune=pick["tune"])
     pts = b.points()
     for _ in range(warmup):
         b.step(1)
@@ -197,13 +200,22 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     nsf.timer_enable(None)
     d = b.diagnostics()
     nitems, nblocks = b.info()
-    per_pt = FAMILY_BYTES["sn_fused"][0 if precision == "f64" else 1] * 3
+    # algorithmic bytes per point and step of the batched stages: in double
+    # precision with 16-row tiles the first substep reads the accumulator
+    # from q and the third leaves it unwritten (but in a call's last step)
+    cfg = b.config()
+    if precision == "f64" and cfg["tile_y"] == 16:
+        per_pt = (FAMILY_BYTES["sn_fused_first"][0] + FAMILY_BYTES["sn_fused"][0]
+                  + FAMILY_BYTES["sn_fused_last"][0])
+    else:
+        per_pt = FAMILY_BYTES["sn_fused"][0 if precision == "f64" else 1] * 3
     avg_s = ms / max(c, 1) / 1e3
     out = {
         "instances": len(insts), "points": pts, "precision": precision, "steps": steps,
         "ms_per_step": (t1 - t0) * 1e3 / steps,
         "pt_rhs_per_s": pts * 3 * steps / (t1 - t0),
         "work_items": nitems, "persistent_blocks": nblocks,
+        "batch_autotune": pick, "batch_config": b.config(),
         "roofline": {"bound": "hbm", "kernel": "ra_batch (3 stage launches per graph replay)",
                      "achieved": round(per_pt * pts / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(per_pt * pts / avg_s / 1e9 / HBM_PEAK_GBS, 4),

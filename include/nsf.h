@@ -126,10 +126,18 @@ typedef struct {
  *         the residual kernel (needs the ping-pong copy of q in `work`).
  *   naive: 1 = use the untiled per-point kernels (reference GPU path): one
  *         kernel per store set, so RA and SN run the same untiled kernel,
- *         and so do RS and SS. */
+ *         and so do RS and SS;
+ *   gstore: SS/RS only, which velocity gradients G_ab = du_a/dx_b are
+ *         stored in work arrays (the others are formed in the residual
+ *         kernel: thread-local in SS, at each use in RS). 0 = the
+ *         algorithm's own set (the nine gradients; on a single-plane grid
+ *         the four in-plane ones, the paper's 2D count); 9 = all nine;
+ *         3 = the three diagonal ones; 4 = the four in-plane ones
+ *         (single-plane grids only). The untiled kernels need 0 or 9.
+ *         NSF_EINVAL for other values or other algorithms. */
 typedef struct {
-    int32_t block_x, block_y, zchunk, fuse, naive;
-    int32_t reserved[3];
+    int32_t block_x, block_y, zchunk, fuse, naive, gstore;
+    int32_t reserved[2];
 } nsf_tuning;
 
 const char *nsf_status_string(int status);
@@ -219,18 +227,25 @@ int nsf_diagnostics_noalloc(const nsf_grid *g, const nsf_phys *phys, int precisi
  * Searches the paper's store-versus-recompute trade-off (Section 2: which
  * derivatives to store in work arrays, which to recompute; the
  * conclusion's point that the best algorithm depends on the machine) made
- * searchable: algorithm BL / RA (primitives stored, or recomputed in the
- * tile with the update fused) / SS, crossed with the tile height and
- * z-chunk of the z-sweeping kernels. Every candidate is first checked
- * against the untiled reference residual on a seeded perturbed
- * Taylor-Green state of the same grid (relative max-norm difference at most
- * 1e-10 in double, 1e-3 in single precision); only passing candidates are
- * timed (`steps` RK steps each). Candidates within 2% of the fastest count
- * as ties, resolved toward the default tuning and then the larger z-chunk.
- * The winner is recorded for NSF_AUTO and,
- * if cache_path is not NULL, appended as one JSON line to that file.
- * Synchronous. Allocates its own device buffers (about 4 states and the
- * largest candidate's work) for the duration of the call. */
+ * searchable: the store set (no derivative arrays: SN, RA; the velocity
+ * gradients: SS, RS with all nine or the three diagonal ones, or on a
+ * single-plane grid the four in-plane ones or all nine), whether the
+ * derivatives not stored are thread-local values (SN, SS) or formed at each
+ * use (RA, RS), the primitives stored or recomputed in the tile with the RK
+ * update fused (SN, RA), and BL, crossed with the tile height and z-chunk of
+ * the z-sweeping kernels. Every candidate is first checked, per field,
+ * against a reference residual on a seeded perturbed Taylor-Green state of
+ * the same grid: in double precision the untiled kernels', at 1e-10
+ * relative max-norm difference; in single precision the double-precision
+ * untiled residual of the same single-precision state, within 4 times the
+ * change that rounding the state to single precision makes to that
+ * residual. Only passing candidates are timed (`steps` RK steps each, from
+ * the same initial state and accumulator). Candidates within 2% of the
+ * fastest count as ties, resolved toward the default tuning and then the
+ * larger z-chunk. The winner is recorded for NSF_AUTO and, if cache_path
+ * is not NULL, appended as one JSON line to that file. Synchronous.
+ * Allocates its own device buffers (four to six states and the largest
+ * candidate's work) for the duration of the call. */
 #define NSF_TUNE_QUICK 1 /* skip BL and the untiled kernels */
 typedef struct {
     int32_t variant;
@@ -242,8 +257,9 @@ typedef struct {
 int nsf_autotune(const nsf_grid *g, const nsf_phys *phys, int precision, int flags, int32_t steps,
                  const char *cache_path, nsf_tune_result *best, void *stream);
 /* Load gfx950 entries of a cache file written by nsf_autotune (later lines
- * override earlier ones). Returns the number of entries loaded, or an
- * error status. */
+ * override earlier ones). A line that names no configuration the library
+ * runs on its grid (algorithm, tile height, z-chunk, flags, store set) is
+ * skipped. Returns the number of entries loaded, or an error status. */
 int nsf_tune_load(const char *cache_path);
 /* The recorded choice for a grid and precision (NSF_EUNSUPPORTED if none). */
 int nsf_tune_get(const nsf_grid *g, int precision, nsf_tune_result *out);
@@ -270,15 +286,47 @@ int nsf_batch_create(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
                      int precision, void *const *q, double *const *q_acc, void *work,
                      size_t work_bytes, void *stream, nsf_batch **out);
 
-/* As nsf_batch_create with implementation knobs (block_y selects the tile
- * height 8 or 16 of the stage kernel; other fields are ignored). */
+/* As nsf_batch_create with implementation knobs: block_y selects the tile
+ * height 8 or 16 of the stage kernel (0: 16 in double, 8 in single
+ * precision), zchunk the planes per tile for every instance (clamped to its
+ * grid; 0: 48, or 64 from 256 planes up, or the whole grid below 64);
+ * other fields are ignored. NSF_EINVAL for other values. */
 int nsf_batch_create_tuned(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
                            const double *dt, int precision, const nsf_tuning *tune, void *const *q,
                            double *const *q_acc, void *work, size_t work_bytes, void *stream,
                            nsf_batch **out);
 
+/* As nsf_batch_create_tuned with the algorithm of the fused stage kernel:
+ * NSF_SN (the other entry points) or NSF_RA (derivatives formed where each
+ * equation uses them); NSF_EUNSUPPORTED for others. */
+int nsf_batch_create_variant(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
+                             const double *dt, int precision, int variant, const nsf_tuning *tune,
+                             void *const *q, double *const *q_acc, void *work, size_t work_bytes,
+                             void *stream, nsf_batch **out);
+
+/* Autotuner of the batched form (the paper's store-versus-recompute choice
+ * and the tile knobs, searched on the batch itself): for the ensemble of
+ * `count` instances (grids, phys, dt as for nsf_batch_create) it times
+ * `steps` graph replays of every candidate -- stage algorithm SN or RA,
+ * tile height 16 or 8, z-chunks of the default rule or 16, 32, 64 planes --
+ * on its own seeded Taylor-Green states, after checking each candidate's
+ * first step against the first candidate's (SN, 16 rows, default chunks)
+ * per instance and field (1e-10 relative in double, 1e-5 in single
+ * precision). Candidates within 2% of the fastest count as ties, resolved
+ * toward SN, 16 rows and the default chunks. Writes the winner to
+ * *best_variant and *best_tune (for nsf_batch_create_variant) and its rate
+ * in grid-point RHS evaluations per second to *best_pt_rhs_per_s (may be
+ * NULL). Synchronous; allocates five ensemble states and a batch work
+ * buffer for the duration of the call. */
+int nsf_batch_autotune(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
+                       const double *dt, int precision, int32_t steps, int32_t *best_variant,
+                       nsf_tuning *best_tune, double *best_pt_rhs_per_s, void *stream);
+
 /* Advance every instance nsteps steps by replaying the captured graph on
- * `stream`. Asynchronous. */
+ * `stream`; on completion q and q_acc hold the new states (in double
+ * precision with 16-row tiles, the steps before the last replay a second
+ * graph whose third substep leaves q_acc unwritten, as nsf_rk_step does).
+ * Asynchronous. */
 int nsf_batch_step(nsf_batch *b, int32_t nsteps, void *stream);
 
 /* The same stage launches issued directly (no graph); same results. */
@@ -290,6 +338,10 @@ int nsf_batch_diagnostics(nsf_batch *b, double *out, void *stream);
 
 /* Work-list size and persistent grid size of the stage launches. */
 int nsf_batch_info(const nsf_batch *b, int32_t *nitems, int32_t *nblocks);
+
+/* The batch's stage algorithm (NSF_SN or NSF_RA), tile height and each
+ * instance's z-chunk (zchunk: host array of `count` entries). */
+int nsf_batch_config(const nsf_batch *b, int32_t *variant, int32_t *tile_y, int32_t *zchunk);
 
 int nsf_batch_destroy(nsf_batch *b);
 

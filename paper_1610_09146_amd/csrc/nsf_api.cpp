@@ -130,6 +130,34 @@ int tile_y_of(const Dims& d, const nsf_tuning* tune, int es) {
     return tune && (tune->block_y == 8 || tune->block_y == 16) ? tune->block_y : default_tile_y(es, d);
 }
 
+// Store set of the stored-gradient algorithms (nsf_tuning.gstore): 9 = the
+// nine velocity gradients (the paper's 3D set), 3 = the three diagonal ones,
+// 4 = the four in-plane ones (single-plane grids only, the paper's 2D count);
+// 0 = the algorithm's own, nine in 3D and four on a single plane. The
+// untiled kernels store all nine.
+int gmask_of(const Dims& d, int variant, const nsf_tuning* tune) {
+    if (variant != NSF_SS && variant != NSF_RS) return 0;
+    if (tune && tune->naive) return kGradAll;
+    const int g = tune ? tune->gstore : 0;
+    if (g == 3) return kGradDiag;
+    if (g == 4 || (g == 0 && d.nz == 1)) return kGradPlane;
+    return kGradAll;
+}
+
+int validate_tune(const Dims& d, int variant, const nsf_tuning* tune) {
+    if (!tune || variant == NSF_AUTO) return NSF_OK;
+    const int g = tune->gstore;
+    if (g != 0 && g != 3 && g != 4 && g != 9)
+        return fail(NSF_EINVAL, "tuning gstore %d: 0, 3, 4 or 9", g);
+    if (g != 0 && variant != NSF_SS && variant != NSF_RS)
+        return fail(NSF_EINVAL, "tuning gstore applies to SS and RS only");
+    if (g == 4 && d.nz != 1)
+        return fail(NSF_EINVAL, "the four in-plane gradients store set needs a single-plane grid");
+    if ((g == 3 || g == 4) && tune->naive)
+        return fail(NSF_EUNSUPPORTED, "the untiled kernels store all nine gradients");
+    return NSF_OK;
+}
+
 bool wants_fused(int variant, const nsf_tuning* tune) {
     return (variant == NSF_RA || variant == NSF_SN) && tune && tune->fuse && !tune->naive;
 }
@@ -152,11 +180,11 @@ void resolve(const Dims& d, int precision, int* variant, const nsf_tuning** tune
 }
 bool is_precision(int p) { return p == NSF_F64 || p == NSF_F32; }
 
-int deriv_arrays(int variant) {
+int deriv_arrays(const Dims& d, int variant, const nsf_tuning* tune) {
     switch (variant) {
         case NSF_BL: return 60;
         case NSF_SS:
-        case NSF_RS: return 9;
+        case NSF_RS: return __builtin_popcount(gmask_of(d, variant, tune));
         default: return 0;
     }
 }
@@ -168,7 +196,7 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     size_t off = 0;
     L.prim = off;
     off = align_up(off + 5 * d.npts * es);
-    L.nderiv = deriv_arrays(variant);
+    L.nderiv = deriv_arrays(d, variant, tune);
     L.deriv = off;
     off = align_up(off + (size_t)L.nderiv * d.npts * es);
     L.prod = off;
@@ -288,9 +316,10 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
                 launch_ss_grad_naive<T>(d, c, prim, grad, s);
                 launch_ss_naive<T>(d, c, q, prim, grad, r, s);
             } else {
-                launch_ss_grad<T>(d, c, prim, grad, s);
+                const int gm = gmask_of(d, variant, tune);
+                launch_ss_grad<T>(d, c, prim, grad, gm, s);
                 launch_ss_zsweep<T>(d, c, q, prim, grad, r, zchunk_of(d, tune),
-                                    tile_y_of(d, tune, sizeof(T)), s, variant == NSF_RS);
+                                    tile_y_of(d, tune, sizeof(T)), s, variant == NSF_RS, gm);
             }
             break;
         }
@@ -395,6 +424,7 @@ int nsf_workspace_bytes(const nsf_grid* g, int variant, int precision, const nsf
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!bytes) return fail(NSF_EINVAL, "bytes is NULL");
+    if ((rc = validate_tune(d, variant, tune))) return rc;
     nsf_tuning store;
     resolve(d, precision, &variant, &tune, &store);
     *bytes = layout_for(d, variant, precision, tune).total;
@@ -436,6 +466,7 @@ int nsf_rhs(const nsf_grid* g, const nsf_phys* phys, int variant, int precision,
     if (!is_variant(variant)) return fail(NSF_EINVAL, "variant %d", variant);
     if (!is_precision(precision)) return fail(NSF_EINVAL, "precision %d", precision);
     if (!q || !r || !work) return fail(NSF_EINVAL, "q, r and work must be non-NULL");
+    if ((rc = validate_tune(d, variant, tune))) return rc;
     nsf_tuning store;
     resolve(d, precision, &variant, &tune, &store);
     const Layout L = layout_for(d, variant, precision, tune);
@@ -463,6 +494,7 @@ int rk_entry(const nsf_grid* g, const nsf_phys* phys, int variant, int precision
     if (!q || !q_acc || !r || !work) return fail(NSF_EINVAL, "q, q_acc, r and work must be non-NULL");
     if (nsteps < 0) return fail(NSF_EINVAL, "nsteps %d", nsteps);
     if (!std::isfinite(dt)) return fail(NSF_EINVAL, "dt not finite");
+    if ((rc = validate_tune(d, variant, tune))) return rc;
     nsf_tuning store;
     resolve(d, precision, &variant, &tune, &store);
     const Layout L = layout_for(d, variant, precision, tune);

@@ -21,6 +21,8 @@ struct nsf_batch {
     int nitems = 0;
     int nblocks = 0;
     int tile_y = 8;
+    int recompute = 0;        // stage kernel: 1 = RA, 0 = SN
+    std::vector<int> zchunk;  // per instance
     std::vector<Dims> dims;
     std::vector<nsf_phys> phys;
     std::vector<void*> q;
@@ -30,8 +32,10 @@ struct nsf_batch {
     int2* items_dev = nullptr;  // items in workgroup order
     int* offs_dev = nullptr;     // workgroup b runs items [offs[b], offs[b+1])
     hipStream_t cap = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;      // one step, storing q_acc in its third substep
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_ns = nullptr;   // double-precision 16-row tiles: the same step
+    hipGraphExec_t exec_ns = nullptr;  // without that store (every step of a call but the last)
 };
 
 namespace {
@@ -142,7 +146,7 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
         bd.qacc = qacc[i];
         bd.dt = dt[i];
         int tx, ty, tz, zc;
-        tile_counts(d, batch_zchunk(d), b->tile_y, &tx, &ty, &tz, &zc);
+        tile_counts(d, b->zchunk[i], b->tile_y, &tx, &ty, &tz, &zc);
         bd.zchunk = zc;
         bd.tiles_x = tx;
         bd.tiles_y = ty;
@@ -172,15 +176,20 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
 }
 
 template <typename T>
-void enqueue_step(nsf_batch* b, hipStream_t s) {
+void enqueue_step(nsf_batch* b, hipStream_t s, int store_acc) {
     for (int st = 0; st < 3; ++st)
         launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->offs_dev, st,
-                           b->nblocks, b->tile_y, s);
+                           b->nblocks, b->tile_y, s, b->recompute != 0, store_acc);
 }
+
+// whether the stage kernel can leave q_acc unwritten (see launch_ra_batch)
+bool saves_acc(const nsf_batch* b) { return b->precision == NSF_F64 && b->tile_y == 16; }
 
 void release(nsf_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_ns) (void)hipGraphExecDestroy(b->exec_ns);
+    if (b->graph_ns) (void)hipGraphDestroy(b->graph_ns);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->desc_dev) (void)hipFree(b->desc_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
@@ -207,18 +216,23 @@ int nsf_batch_workspace_bytes(int32_t count, const nsf_grid* grids, int precisio
 int nsf_batch_create(int32_t count, const nsf_grid* grids, const nsf_phys* phys, const double* dt,
                      int precision, void* const* q, double* const* q_acc, void* work,
                      size_t work_bytes, void* stream, nsf_batch** out) {
-    return nsf_batch_create_tuned(count, grids, phys, dt, precision, nullptr, q, q_acc, work,
-                                  work_bytes, stream, out);
+    return nsf_batch_create_variant(count, grids, phys, dt, precision, NSF_SN, nullptr, q, q_acc,
+                                    work, work_bytes, stream, out);
 }
 
 int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
                            const double* dt, int precision, const nsf_tuning* tune, void* const* q,
                            double* const* q_acc, void* work, size_t work_bytes, void* stream,
                            nsf_batch** out) {
+    return nsf_batch_create_variant(count, grids, phys, dt, precision, NSF_SN, tune, q, q_acc, work,
+                                    work_bytes, stream, out);
+}
+
+int nsf_batch_create_variant(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
+                             const double* dt, int precision, int variant, const nsf_tuning* tune,
+                             void* const* q, double* const* q_acc, void* work, size_t work_bytes,
+                             void* stream, nsf_batch** out) {
     (void)stream;
-    const int tile_y = tune && (tune->block_y == 8 || tune->block_y == 16)
-                           ? tune->block_y
-                           : (precision == NSF_F64 ? 16 : 8);
     if (!out) return bfail(NSF_EINVAL, "batch: out NULL");
     *out = nullptr;
     std::vector<Dims> dims;
@@ -226,6 +240,10 @@ int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys*
     if (rc) return rc;
     if (!phys || !dt || !q || !q_acc || !work) return bfail(NSF_EINVAL, "batch: NULL argument");
     if (precision != NSF_F64 && precision != NSF_F32) return bfail(NSF_EINVAL, "batch: precision");
+    if (variant != NSF_SN && variant != NSF_RA)
+        return bfail(NSF_EUNSUPPORTED, "batch: the batched stage is SN or RA");
+    if (tune && ((tune->block_y != 0 && tune->block_y != 8 && tune->block_y != 16) || tune->zchunk < 0))
+        return bfail(NSF_EINVAL, "batch: block_y 0, 8 or 16 and zchunk >= 0");
     for (int i = 0; i < count; ++i) {
         const nsf_phys& p = phys[i];
         if (!(p.Re > 0) || !(p.Ma > 0) || !(p.Pr > 0) || !(p.gamma > 1) || !std::isfinite(dt[i]))
@@ -243,12 +261,17 @@ int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys*
     b->phys.assign(phys, phys + count);
     b->q.assign(q, q + count);
     b->diag_partial.resize(count);
-    b->tile_y = tile_y;
+    b->recompute = variant == NSF_RA;
+    b->tile_y = tune && tune->block_y ? tune->block_y : (precision == NSF_F64 ? 16 : 8);
+    b->zchunk.resize(count);
+    for (int i = 0; i < count; ++i)
+        b->zchunk[i] = tune && tune->zchunk > 0 ? std::min(tune->zchunk, dims[i].nz)
+                                                : batch_zchunk(dims[i]);
     int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = precision == NSF_F64 ? batch_blocks_per_cu<double>(b->tile_y)
-                                            : batch_blocks_per_cu<float>(b->tile_y);
+    const int per_cu = precision == NSF_F64 ? batch_blocks_per_cu<double>(b->tile_y, b->recompute)
+                                            : batch_blocks_per_cu<float>(b->tile_y, b->recompute);
     if (e != hipSuccess || cus < 1 || per_cu < 1) { release(b); return bfail(NSF_EHIP, "batch: occupancy query failed"); }
     b->nblocks = (cus * per_cu) / 8 * 8;  // a multiple of the XCD count
     if (b->nblocks < 8) b->nblocks = 8;
@@ -257,15 +280,21 @@ int nsf_batch_create_tuned(int32_t count, const nsf_grid* grids, const nsf_phys*
              : build_tables<float>(b, dims, phys, dt, q, q_acc, (char*)work);
     if (rc) { release(b); return rc; }
 
-    // capture one step (three stage launches) into a graph on a private stream
+    // capture one step (three stage launches) into a graph on a private
+    // stream; where the third substep can skip the q_acc store, also the
+    // step without it
     e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        if (precision == NSF_F64) enqueue_step<double>(b, b->cap);
-        else enqueue_step<float>(b, b->cap);
-        e = hipStreamEndCapture(b->cap, &b->graph);
+    for (int k = 0; k < (saves_acc(b) ? 2 : 1) && e == hipSuccess; ++k) {
+        hipGraph_t* g = k == 0 ? &b->graph : &b->graph_ns;
+        hipGraphExec_t* x = k == 0 ? &b->exec : &b->exec_ns;
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            if (precision == NSF_F64) enqueue_step<double>(b, b->cap, k == 0);
+            else enqueue_step<float>(b, b->cap, k == 0);
+            e = hipStreamEndCapture(b->cap, g);
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(x, *g, nullptr, nullptr, 0);
     }
-    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) { release(b); return bfail(NSF_EHIP, hipGetErrorString(e)); }
     *out = b;
     return NSF_OK;
@@ -276,7 +305,7 @@ int nsf_batch_step(nsf_batch* b, int32_t nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     for (int i = 0; i < nsteps; ++i) {
         TimerScope ts("batch_step", s);  // one record per replayed step
-        hipError_t e = hipGraphLaunch(b->exec, s);
+        hipError_t e = hipGraphLaunch(i + 1 < nsteps && b->exec_ns ? b->exec_ns : b->exec, s);
         if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
     }
     return NSF_OK;
@@ -287,8 +316,9 @@ int nsf_batch_step_eager(nsf_batch* b, int32_t nsteps, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     for (int i = 0; i < nsteps; ++i) {
         TimerScope ts("batch_step", s);
-        if (b->precision == NSF_F64) enqueue_step<double>(b, s);
-        else enqueue_step<float>(b, s);
+        const int store = i + 1 == nsteps || !saves_acc(b);
+        if (b->precision == NSF_F64) enqueue_step<double>(b, s, store);
+        else enqueue_step<float>(b, s, store);
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? NSF_OK : bfail(NSF_EHIP, hipGetErrorString(e));
@@ -320,6 +350,14 @@ int nsf_batch_info(const nsf_batch* b, int32_t* nitems, int32_t* nblocks) {
     if (!b || !nitems || !nblocks) return bfail(NSF_EINVAL, "batch_info: NULL argument");
     *nitems = b->nitems;
     *nblocks = b->nblocks;
+    return NSF_OK;
+}
+
+int nsf_batch_config(const nsf_batch* b, int32_t* variant, int32_t* tile_y, int32_t* zchunk) {
+    if (!b || !variant || !tile_y || !zchunk) return bfail(NSF_EINVAL, "batch_config: NULL argument");
+    *variant = b->recompute ? NSF_RA : NSF_SN;
+    *tile_y = b->tile_y;
+    for (int i = 0; i < b->count; ++i) zchunk[i] = b->zchunk[i];
     return NSF_OK;
 }
 

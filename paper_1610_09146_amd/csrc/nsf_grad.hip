@@ -1,5 +1,8 @@
-// SS / RS gradient loop (paper Section 2, RS and SS paragraphs): the nine
-// first derivatives of the velocity, G_ab = D_b u_a, stored in work arrays.
+// SS / RS gradient loop (paper Section 2, RS and SS paragraphs): the first
+// derivatives of the velocity, G_ab = D_b u_a, of a store set (bit 3a + b
+// of the mask GM) stored in work arrays, the stored ones in order of 3a + b:
+// all nine (the paper's 3D set), the three diagonal ones, or the four
+// in-plane ones of a two-dimensional grid (the paper's 2D count).
 // z-marching tiles: the stored velocity of each plane (with a two-point x-y
 // halo) enters a five-plane LDS ring once; x, y and z differences of the
 // centre plane are taken from the ring.
@@ -49,9 +52,12 @@ struct GradArgs {
     int zchunk, tiles_x, tiles_y;
 };
 
-template <typename T>
+template <typename T, int GM>
 __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restrict__ prim,
                                                  T* __restrict__ grad) {
+    // array of gradient (a, b): the number of stored gradients before it
+    auto slot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
+    auto stored = [](int a, int b) { return (GM >> (3 * a + b)) & 1; };
     __shared__ T sV[kRing * 3 * kNPL];
     const Dims d = A.d;
     const size_t n = d.npts;
@@ -120,13 +126,16 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
             for (int a = 0; a < 3; ++a) {
                 const T* F = Vc + a * kNPL;
                 // streamed: the residual sweep reads them back from HBM (7% faster)
-                st_nt(a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]),
-                      grad + (3 * a + 0) * n + o);
-                st_nt(a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]),
-                      grad + (3 * a + 1) * n + o);
-                st_nt(a1z * (Vp1[a * kNPL + own] - Vm1[a * kNPL + own]) +
-                          a2z * (Vp2[a * kNPL + own] - Vm2[a * kNPL + own]),
-                      grad + (3 * a + 2) * n + o);
+                if (stored(a, 0))
+                    st_nt(a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]),
+                          grad + slot(a, 0) * n + o);
+                if (stored(a, 1))
+                    st_nt(a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]),
+                          grad + slot(a, 1) * n + o);
+                if (stored(a, 2))
+                    st_nt(a1z * (Vp1[a * kNPL + own] - Vm1[a * kNPL + own]) +
+                              a2z * (Vp2[a * kNPL + own] - Vm2[a * kNPL + own]),
+                          grad + slot(a, 2) * n + o);
             }
         }
         __syncthreads();
@@ -136,7 +145,8 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
 }  // namespace
 
 template <typename T>
-void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hipStream_t s) {
+void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int gmask,
+                    hipStream_t s) {
     TimerScope ts("ss_grad", s);
     GradArgs<T> a;
     a.d = d;
@@ -145,11 +155,18 @@ void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hip
     a.tiles_x = (d.nx + kTX - 1) / kTX;
     a.tiles_y = (d.ny + kTY - 1) / kTY;
     const int tz = (d.nz + a.zchunk - 1) / a.zchunk;
-    hipLaunchKernelGGL(k_ss_grad<T>, dim3(a.tiles_x * a.tiles_y * tz), dim3(kNT), 0, s, a, prim, grad);
+    const dim3 grid(a.tiles_x * a.tiles_y * tz);
+    if (gmask == kGradDiag)
+        hipLaunchKernelGGL((k_ss_grad<T, kGradDiag>), grid, dim3(kNT), 0, s, a, prim, grad);
+    else if (gmask == kGradPlane)
+        hipLaunchKernelGGL((k_ss_grad<T, kGradPlane>), grid, dim3(kNT), 0, s, a, prim, grad);
+    else
+        hipLaunchKernelGGL((k_ss_grad<T, kGradAll>), grid, dim3(kNT), 0, s, a, prim, grad);
 }
 
-template void launch_ss_grad<float>(const Dims&, const Coef<float>&, const float*, float*, hipStream_t);
-template void launch_ss_grad<double>(const Dims&, const Coef<double>&, const double*, double*,
+template void launch_ss_grad<float>(const Dims&, const Coef<float>&, const float*, float*, int,
+                                    hipStream_t);
+template void launch_ss_grad<double>(const Dims&, const Coef<double>&, const double*, double*, int,
                                      hipStream_t);
 
 }  // namespace nsf

@@ -9,6 +9,13 @@
 
 namespace nsf {
 
+// Store sets of the stored-gradient algorithms (bit 3a + b: G_ab = D_b u_a
+// stored in a work array, the stored ones in order of 3a + b): all nine (the
+// paper's SS and RS in 3D), the three diagonal ones, or the four in-plane
+// ones of a two-dimensional grid (the paper's 2D count; the z gradients
+// vanish there and D_x w, D_y w are formed in the tile).
+constexpr int kGradAll = 0x1FF, kGradDiag = 0x111, kGradPlane = 0x01B;
+
 struct InitParams {
     double gamma, Ma, V0, amp;
     uint64_t seed;
@@ -121,13 +128,16 @@ constexpr int kXCD = 8;  // gfx950: 8 XCDs, workgroups dispatched round-robin
 int default_zchunk(const Dims& d);
 int default_tile_y(int precision_bytes, const Dims& d);
 void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* tz, int* zc);
-// Persistent batched fused stage: items[i] = (instance, tile index), in
-// workgroup order; workgroup b runs items[offs[b]] .. items[offs[b + 1] - 1].
+// Persistent batched fused stage (recompute: RA, else SN): items[i] =
+// (instance, tile index), in workgroup order; workgroup b runs
+// items[offs[b]] .. items[offs[b + 1] - 1].
+// store_acc = 0 lets the double-precision 16-row form leave q_acc unwritten
+// in the third substep (every step but a call's last).
 template <typename T>
 void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
-                     int nblocks, int tile_y, hipStream_t s);
+                     int nblocks, int tile_y, hipStream_t s, bool recompute, int store_acc);
 template <typename T>
-int batch_blocks_per_cu(int tile_y);
+int batch_blocks_per_cu(int tile_y, bool recompute);
 // Residual from stored primitives, no derivative arrays: recompute = true is
 // the recompute-all algorithm RA (every derivative formed where a term uses
 // it, equation by equation), false the store-none algorithm SN (every
@@ -141,10 +151,12 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
 // the store-some algorithm SS (thread-local values).
 template <typename T>
 void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
-                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute);
-// SS gradient loop: G_ab = D_b u_a into nine arrays (z-marching tiles).
+                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute,
+                      int gmask = kGradAll);
+// SS gradient loop: the store set's G_ab = D_b u_a into arrays (z-marching tiles).
 template <typename T>
-void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, hipStream_t s);
+void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int gmask,
+                    hipStream_t s);
 // Fused stage with no derivative arrays (RA with recompute = true, SN
 // otherwise): primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),

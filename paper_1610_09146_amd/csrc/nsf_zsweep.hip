@@ -427,7 +427,7 @@ __device__ __forceinline__ void rc_fence() { asm volatile("" ::: "memory"); }
 template <typename T>
 __device__ __forceinline__ void rc_pin(T& x) { asm volatile("" : "+v"(x)); }
 
-template <typename T, bool SS, bool MON, typename PoffF>
+template <typename T, bool SS, bool MON, int GM, typename PoffF>
 __device__ __forceinline__ void recompute_point(const RcView<T>& v, const Pt<T> Q[5], const T uc[3],
                                                 const Coef<T>& k, const T* grad, size_t n,
                                                 PoffF poff, int z, size_t col, const size_t xnb[4],
@@ -469,16 +469,19 @@ __device__ __forceinline__ void recompute_point(const RcView<T>& v, const Pt<T> 
         return k.b0[B] * g(2) + k.b1[B] * (g(3) + g(1)) + k.b2[B] * (g(4) + g(0));
     };
     const size_t pz = poff(z);
-    // velocity gradient G_ab = D_b u_a: its stored array (RS) or its difference (RA)
+    // stored-gradient forms: whether G_ab is in the store set GM, and its array
+    auto stored = [](int a, int b) { return SS && ((GM >> (3 * a + b)) & 1); };
+    auto slot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
+    // velocity gradient G_ab = D_b u_a: its stored array (RS), or its difference
     auto Gab = [&](int a, int b) -> T {
-        if constexpr (SS) return grad[(3 * a + b) * n + pz + col];
-        else return D1(b, [&](int s) { return Us(a, b, s); });
+        if (stored(a, b)) return grad[slot(a, b) * n + pz + col];
+        return D1(b, [&](int s) { return Us(a, b, s); });
     };
     // D_A(G_cc), A != c: D_A of the stored diagonal gradient (RS), or the
-    // nested difference D_A(D_c u_c) over the staged velocity (RA)
+    // nested difference D_A(D_c u_c) over the staged velocity
     auto DG = [&](int A, int c) -> T {
-        if constexpr (SS) {
-            const int comp = 4 * c;
+        if (stored(c, c)) {
+            const int comp = slot(c, c);
             auto g = [&](int s) -> T {
                 const int m = s < 2 ? s : s - 1;  // xnb / ynb slot of offset s - 2
                 if (A == 0) return grad[comp * n + pz + xnb[m]];
@@ -649,7 +652,7 @@ struct PlaneLds {
 // 3 * DSZ values. Ends with a barrier, so the caller may reuse the LDS for
 // another tile right away.
 template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false,
-          bool RC = false>
+          bool RC = false, int GM = kGradAll>
 __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restrict__ sP,
                                             T* __restrict__ sV, T* __restrict__ sH,
                                             T* __restrict__ sD,
@@ -686,6 +689,11 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // led), D_x u and D_y v in the D ring; the x and y folds skip them
     constexpr int kGskipX = SS ? 0 : (DR ? 0b101 : 0b100);
     constexpr int kGskipY = SS ? 0 : (DR ? 0b110 : 0b100);
+    // stored-gradient forms: array of the stored G_ab (the number of stored
+    // gradients before it in the store set GM)
+    auto gslot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
+    auto gstored = [](int a, int b) { return (GM >> (3 * a + b)) & 1; };
+    constexpr int kG00 = 0, kG11 = __builtin_popcount(GM & 0xF);
 
     const Dims d = A.d;
     const Coef<T> k = A.k;
@@ -787,8 +795,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     if constexpr (SS && !RC) {
 #pragma unroll
         for (int s = 0; s < 5; ++s) {
-            Xs[s] = A.grad[0 * n + poff(z0 - 2 + s) + col];
-            Xw[s] = A.grad[4 * n + poff(z0 - 2 + s) + col];
+            Xs[s] = A.grad[kG00 * n + poff(z0 - 2 + s) + col];
+            Xw[s] = A.grad[kG11 * n + poff(z0 - 2 + s) + col];
         }
     }
     auto leading = [&](const T* V, T& s, T& xw, T& yw, int zz, bool keepD) {
@@ -1039,8 +1047,8 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         }
         T gnx[SS ? 2 : 1];
         if constexpr (SS && !RC) {
-            gnx[0] = A.grad[0 * n + poff(z + 3) + col];
-            gnx[1] = A.grad[4 * n + poff(z + 3) + col];
+            gnx[0] = A.grad[kG00 * n + poff(z + 3) + col];
+            gnx[1] = A.grad[kG11 * n + poff(z + 3) + col];
         }
         // fused form: the accumulator of plane z. The lean single-precision
         // form fetches it here, before the compute, so its latency is
@@ -1068,7 +1076,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         T R[5];
         T om2 = T(0);
         if constexpr (RC) {
-            recompute_point<T, SS, MON>(RcView<T>{Pz, {ring(z - 2), ring(z - 1), Vc, ring(z + 1), ring(z + 2)},
+            recompute_point<T, SS, MON, GM>(RcView<T>{Pz, {ring(z - 2), ring(z - 1), Vc, ring(z + 1), ring(z + 2)},
                                                   ownP, ownV, FOP, RSP, FOV, RSV},
                                         Qz, uc, k, A.grad, n, poff, z, col, xnb, ynb, R, om2);
         } else {
@@ -1164,8 +1172,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int b = 0; b < 3; ++b)
-                    ac.G[a][b] = a == b ? gat(3 * a + b, pz + col)
-                                        : stream_load(Gs + (3 * a + b) * n + pz + col);
+                    if (gstored(a, b))
+                        ac.G[a][b] = a == b ? gat(gslot(a, b), pz + col)
+                                            : stream_load(Gs + gslot(a, b) * n + pz + col);
             auto dxg = [&](int comp) {
                 return D1(gat(comp, pz + xnb[0]), gat(comp, pz + xnb[1]), gat(comp, pz + xnb[2]),
                           gat(comp, pz + xnb[3]), k.a1[0], k.a2[0]);
@@ -1174,8 +1183,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                 return D1(gat(comp, pz + ynb[0]), gat(comp, pz + ynb[1]), gat(comp, pz + ynb[2]),
                           gat(comp, pz + ynb[3]), k.a1[1], k.a2[1]);
             };
-            cross[0] = dxg(4) + dxg(8);
-            cross[1] = dyg(0) + dyg(8);
+            // (a store set without G_zz belongs to a single-plane grid, where
+            // every z difference, hence G_zz, is zero)
+            cross[0] = dxg(gslot(1, 1)) + (gstored(2, 2) ? dxg(gslot(2, 2)) : T(0));
+            cross[1] = dyg(gslot(0, 0)) + (gstored(2, 2) ? dyg(gslot(2, 2)) : T(0));
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], k.a1[2], k.a2[2]) +
                        D1(Xw[0], Xw[1], Xw[3], Xw[4], k.a1[2], k.a2[2]);
         } else {
@@ -1376,7 +1387,7 @@ struct Occ {
     static constexpr int kWaves = (sizeof(T) == 8 || RC) ? 2 : 3;
 };
 
-template <typename T, int TX, int TY, bool FUSED, bool SS, bool MON, bool RC>
+template <typename T, int TX, int TY, bool FUSED, bool SS, bool MON, bool RC, int GM>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T, RC>::kWaves, Occ<T, RC>::kWaves)))
 k_ra_zsweep(ZArgs<T> A) {
@@ -1386,24 +1397,24 @@ k_ra_zsweep(ZArgs<T> A) {
     __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 2 * kPF * G::NHALO : 1];
     __shared__ T sD[d_ring<T, TY, SS, RC>() ? 3 * G::DSZ : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
-    zsweep_tile<T, TX, TY, FUSED, SS, MON, RC>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH, sD,
-                                               sM);
+    zsweep_tile<T, TX, TY, FUSED, SS, MON, RC, GM>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH,
+                                                   sD, sM);
 }
 
 // Persistent batched stage kernel: workgroup b runs its own run of the
 // (instance, tile) items, items[offs[b]] .. items[offs[b + 1] - 1], from a
 // schedule built on the host (one band of neighbouring tiles per XCD, evened
 // out by item cost). Stage s reads state s of the rotation q -> qb -> qc -> q.
-template <typename T, int TX, int TY>
+template <typename T, int TX, int TY, bool RC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
-                               amdgpu_waves_per_eu(Occ<T>::kWaves, Occ<T>::kWaves)))
+                               amdgpu_waves_per_eu(Occ<T, RC>::kWaves, Occ<T, RC>::kWaves)))
 k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items,
-           const int* __restrict__ offs, int stage) {
+           const int* __restrict__ offs, int stage, int store_acc) {
     using G = Geom<TX, TY>;
     __shared__ T sP[2 * kPF * G::NPL];
-    __shared__ T sV[ring_slots<T, TY, true, false>() * 3 * G::NPL];
+    __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, true, false, RC>() * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, true>() ? 2 * kPF * G::NHALO : 1];
-    __shared__ T sD[d_ring<T, TY, false>() ? 3 * G::DSZ : 1];
+    __shared__ T sD[d_ring<T, TY, false, RC>() ? 3 * G::DSZ : 1];
     const int first = offs[blockIdx.x], last = offs[blockIdx.x + 1];
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
     const double B_[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
@@ -1419,8 +1430,12 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.grad = nullptr;
         A.r = nullptr;
         A.qacc = bd.qacc;
-        A.qacc_in = bd.qacc;
-        A.acc_store = 1;
+        // double precision, 16-row tiles: the first substep reads the
+        // accumulator from q (equal at a step boundary), and the third
+        // leaves q_acc unwritten unless store_acc (the last step of a call)
+        constexpr bool kSave = sizeof(T) == 8 && TY == 16;
+        A.qacc_in = (kSave && stage == 0) ? reinterpret_cast<const double*>(bd.q) : bd.qacc;
+        A.acc_store = (kSave && stage == 2) ? store_acc : 1;
         A.a_dt = stage < 2 ? A_[stage] * bd.dt : 0.0;
         A.b_dt = B_[stage] * bd.dt;
         A.last = stage == 2;
@@ -1428,12 +1443,12 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.mpart = nullptr;
         A.tiles_x = bd.tiles_x;
         A.tiles_y = bd.tiles_y;
-        zsweep_tile<T, TX, TY, true>(A, it.y, sP, sV, sH, sD);
+        zsweep_tile<T, TX, TY, true, false, false, RC>(A, it.y, sP, sV, sH, sD);
     }
 }
 
 template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false,
-          bool RC = false>
+          bool RC = false, int GM = kGradAll>
 void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     ZArgs<T> a = a0;
     const Dims& d = a.d;
@@ -1442,8 +1457,8 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
     a.tiles_y = (d.ny + TY - 1) / TY;
     const int tiles_z = (d.nz + a.zchunk - 1) / a.zchunk;
     const unsigned nb = (unsigned)(a.tiles_x * a.tiles_y * tiles_z);
-    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS, MON, RC>), dim3(nb), dim3(TX * TY), 0, s,
-                       a);
+    hipLaunchKernelGGL((k_ra_zsweep<T, TX, TY, FUSED, SS, MON, RC, GM>), dim3(nb), dim3(TX * TY), 0,
+                       s, a);
 }
 
 }  // namespace
@@ -1484,9 +1499,20 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     }
 }
 
+template <typename T, int GM>
+void launch_ss_set(const ZArgs<T>& a, int zchunk, int tile_y, hipStream_t s, bool recompute) {
+    if (recompute) {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, true, GM>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, true, false, true, GM>(a, zchunk, s);
+    } else {
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, false, GM>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, true, false, false, GM>(a, zchunk, s);
+    }
+}
+
 template <typename T>
 void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
-                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute) {
+                      T* r, int zchunk, int tile_y, hipStream_t s, bool recompute, int gmask) {
     TimerScope ts(recompute ? "rs_zsweep" : "ss_zsweep", s);
     ZArgs<T> a{};
     a.d = d;
@@ -1495,33 +1521,44 @@ void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.prim = prim;
     a.grad = grad;
     a.r = r;
-    if (recompute) {
-        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, true>(a, zchunk, s);
-        else launch_tiles<T, kTX, 8, false, true, false, true>(a, zchunk, s);
-    } else {
-        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true>(a, zchunk, s);
-        else launch_tiles<T, kTX, 8, false, true>(a, zchunk, s);
-    }
+    if (gmask == kGradDiag) launch_ss_set<T, kGradDiag>(a, zchunk, tile_y, s, recompute);
+    else if (gmask == kGradPlane) launch_ss_set<T, kGradPlane>(a, zchunk, tile_y, s, recompute);
+    else launch_ss_set<T, kGradAll>(a, zchunk, tile_y, s, recompute);
 }
 
 template <typename T>
 void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
-                     int nblocks, int tile_y, hipStream_t s) {
+                     int nblocks, int tile_y, hipStream_t s, bool recompute, int store_acc) {
     TimerScope ts("ra_batch", s);
-    if (tile_y == 16)
-        hipLaunchKernelGGL((k_ra_batch<T, kTX, 16>), dim3(nblocks), dim3(kTX * 16), 0, s, desc,
-                           items, offs, stage);
-    else
-        hipLaunchKernelGGL((k_ra_batch<T, kTX, 8>), dim3(nblocks), dim3(kTX * 8), 0, s, desc, items,
-                           offs, stage);
+    const dim3 g(nblocks);
+    if (recompute) {
+        if (tile_y == 16)
+            hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, true>), g, dim3(kTX * 16), 0, s, desc, items,
+                               offs, stage, store_acc);
+        else
+            hipLaunchKernelGGL((k_ra_batch<T, kTX, 8, true>), g, dim3(kTX * 8), 0, s, desc, items,
+                               offs, stage, store_acc);
+    } else if (tile_y == 16) {
+        hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, false>), g, dim3(kTX * 16), 0, s, desc, items,
+                           offs, stage, store_acc);
+    } else {
+        hipLaunchKernelGGL((k_ra_batch<T, kTX, 8, false>), g, dim3(kTX * 8), 0, s, desc, items,
+                           offs, stage, store_acc);
+    }
 }
 
 template <typename T>
-int batch_blocks_per_cu(int tile_y) {
+int batch_blocks_per_cu(int tile_y, bool recompute) {
     int nb = 0;
-    hipError_t e = tile_y == 16
-        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16>, kTX * 16, 0)
-        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 8>, kTX * 8, 0);
+    hipError_t e;
+    if (recompute)
+        e = tile_y == 16
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16, true>, kTX * 16, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 8, true>, kTX * 8, 0);
+    else
+        e = tile_y == 16
+            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16, false>, kTX * 16, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 8, false>, kTX * 8, 0);
     return e == hipSuccess ? nb : 0;
 }
 
@@ -1588,12 +1625,12 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
 
 #define NSF_INST(T)                                                                          \
     template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, const int*, int, int, int, \
-                                     hipStream_t);                                            \
-    template int batch_blocks_per_cu<T>(int);                                                 \
+                                     hipStream_t, bool, int);                                 \
+    template int batch_blocks_per_cu<T>(int, bool);                                           \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
                                       int, int, hipStream_t, bool);                         \
     template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
-                                      const T*, T*, int, int, hipStream_t, bool);           \
+                                      const T*, T*, int, int, hipStream_t, bool, int);      \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
                                      const StageCoef&, int, int, hipStream_t, double*, bool);
 NSF_INST(float)

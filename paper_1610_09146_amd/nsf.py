@@ -59,7 +59,7 @@ class TGV(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("block_x", ctypes.c_int32), ("block_y", ctypes.c_int32),
                 ("zchunk", ctypes.c_int32), ("fuse", ctypes.c_int32), ("naive", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("gstore", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class TuneResult(ctypes.Structure):
@@ -105,6 +105,13 @@ def lib() -> ctypes.CDLL:
         L.nsf_batch_step_eager.argtypes = [vp, i32, vp]
         L.nsf_batch_diagnostics.argtypes = [vp, ctypes.POINTER(d), vp]
         L.nsf_batch_info.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.nsf_batch_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                       ctypes.POINTER(i32)]
+        L.nsf_batch_create_variant.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int,
+                                               ctypes.c_int, Tu, ctypes.POINTER(vp),
+                                               ctypes.POINTER(vp), vp, sz, vp, ctypes.POINTER(vp)]
+        L.nsf_batch_autotune.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, i32,
+                                         ctypes.POINTER(i32), Tu, ctypes.POINTER(d), vp]
         L.nsf_batch_destroy.argtypes = [vp]
         L.nsf_batch_create_tuned.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, Tu,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
@@ -148,7 +155,7 @@ def _tuning(tune: dict | None):
     if not tune:
         return None
     t = Tuning(int(tune.get("block_x", 0)), int(tune.get("block_y", 0)), int(tune.get("zchunk", 0)),
-               int(tune.get("fuse", 0)), int(tune.get("naive", 0)))
+               int(tune.get("fuse", 0)), int(tune.get("naive", 0)), int(tune.get("gstore", 0)))
     return ctypes.byref(t)
 
 
@@ -269,11 +276,26 @@ def diagnostics_noalloc(shape, phys, precision, q, stream=None, check: bool = Tr
     return np.array(out[:], dtype=np.float64)
 
 
+def batch_autotune(instances, precision, steps: int = 3, stream=None) -> dict:
+    """nsf_batch_autotune on an ensemble (list of instance dicts): the
+    fastest parity-checked (stage algorithm, tile height, z-chunk)."""
+    n = len(instances)
+    grids = (Grid * n)(*[_grid(i["shape"]) for i in instances])
+    phys = (Phys * n)(*[_phys(i["phys"]) for i in instances])
+    dts = (ctypes.c_double * n)(*[float(i["dt"]) for i in instances])
+    v, t, rate = ctypes.c_int32(0), Tuning(), ctypes.c_double(0)
+    _check(lib().nsf_batch_autotune(n, grids, phys, dts, _precision(precision), int(steps),
+                                    ctypes.byref(v), ctypes.byref(t), ctypes.byref(rate),
+                                    _stream(stream)), "nsf_batch_autotune")
+    return {"variant": VARIANT_NAMES.get(int(v.value)),
+            "tune": {"block_y": t.block_y, "zchunk": t.zchunk}, "pt_rhs_per_s": float(rate.value)}
+
+
 def _tune_dict(r: TuneResult) -> dict:
     t = r.tune
     return {"variant": VARIANT_NAMES.get(int(r.variant), int(r.variant)),
             "tune": {"block_x": t.block_x, "block_y": t.block_y, "zchunk": t.zchunk,
-                     "fuse": t.fuse, "naive": t.naive},
+                     "fuse": t.fuse, "naive": t.naive, "gstore": t.gstore},
             "pt_rhs_per_s": float(r.pt_rhs_per_s), "parity_rel_err": float(r.parity_rel_err)}
 
 
@@ -378,7 +400,8 @@ class Batch:
     Per-instance q / q_acc tensors and the shared work buffer are allocated
     with torch and kept alive by this object."""
 
-    def __init__(self, instances, precision="f64", device="cuda", stream=None):
+    def __init__(self, instances, precision="f64", device="cuda", stream=None, tune=None,
+                 variant="SN"):
         self.instances = list(instances)
         self.precision = _precision(precision)
         self.count = len(self.instances)
@@ -403,9 +426,15 @@ class Batch:
         self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
         handle = ctypes.c_void_p(0)
         torch.cuda.synchronize()
-        _check(L.nsf_batch_create(self.count, grids, phys, dts, self.precision, qp, ap,
-                                  _ptr(self.work), int(nb.value), _stream(stream),
-                                  ctypes.byref(handle)), "nsf_batch_create")
+        if tune or variant != "SN":
+            _check(L.nsf_batch_create_variant(self.count, grids, phys, dts, self.precision,
+                                              _variant(variant), _tuning(tune), qp, ap,
+                                              _ptr(self.work), int(nb.value), _stream(stream),
+                                              ctypes.byref(handle)), "nsf_batch_create_variant")
+        else:
+            _check(L.nsf_batch_create(self.count, grids, phys, dts, self.precision, qp, ap,
+                                      _ptr(self.work), int(nb.value), _stream(stream),
+                                      ctypes.byref(handle)), "nsf_batch_create")
         self.handle = handle
 
     def step(self, nsteps: int = 1, graph: bool = True, stream=None) -> None:
@@ -422,6 +451,15 @@ class Batch:
         a, b = ctypes.c_int32(0), ctypes.c_int32(0)
         _check(lib().nsf_batch_info(self.handle, ctypes.byref(a), ctypes.byref(b)), "nsf_batch_info")
         return int(a.value), int(b.value)
+
+    def config(self) -> dict:
+        """Stage algorithm, tile height and per-instance z-chunks (nsf_batch_config)."""
+        v, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+        zc = (ctypes.c_int32 * self.count)()
+        _check(lib().nsf_batch_config(self.handle, ctypes.byref(v), ctypes.byref(ty), zc),
+               "nsf_batch_config")
+        return {"variant": VARIANT_NAMES.get(int(v.value)), "tile_y": int(ty.value),
+                "zchunk": [int(x) for x in zc]}
 
     def points(self) -> int:
         return sum(int(np.prod(i["shape"])) for i in self.instances)

@@ -199,3 +199,48 @@ def test_noalloc_rejects_before_any_work(nsf):
     rc = L.nsf_diagnostics_noalloc(ctypes.byref(small), ctypes.byref(nsf._phys(phys)), 0, dummy,
                                    None, None)
     assert rc == nsf.EINVAL
+
+
+def test_store_set_workspace_and_validation(nsf):
+    """The store set of SS / RS (nsf_tuning.gstore) sizes the gradient
+    arrays: nine by default in 3D, three for the diagonal set, four in-plane
+    ones on a single-plane grid; other values, other algorithms and the
+    in-plane set on a 3D grid are rejected."""
+    n = 32
+    npts = n ** 3
+    ra = nsf.workspace_bytes((n, n, n), "RA", "f64")
+    for v in ("SS", "RS"):
+        assert nsf.workspace_bytes((n, n, n), v, "f64") - ra >= 9 * npts * 8
+        d3 = nsf.workspace_bytes((n, n, n), v, "f64", {"gstore": 3}) - ra
+        assert 3 * npts * 8 <= d3 < 4 * npts * 8
+        assert nsf.workspace_bytes((n, n, n), v, "f64", {"gstore": 9}) - ra >= 9 * npts * 8
+    p2 = 40 * 36
+    ra2 = nsf.workspace_bytes((40, 36, 1), "RA", "f64")
+    ss2 = nsf.workspace_bytes((40, 36, 1), "SS", "f64") - ra2
+    assert 4 * p2 * 8 <= ss2 < 5 * p2 * 8
+    assert nsf.workspace_bytes((40, 36, 1), "SS", "f64", {"gstore": 9}) - ra2 >= 9 * p2 * 8
+    for shape, v, tune in (((n, n, n), "SS", {"gstore": 4}), ((n, n, n), "SS", {"gstore": 5}),
+                           ((n, n, n), "SN", {"gstore": 3}), ((n, n, n), "BL", {"gstore": 9})):
+        with pytest.raises(nsf.NsfError) as ei:
+            nsf.workspace_bytes(shape, v, "f64", tune)
+        assert ei.value.code == nsf.EINVAL
+
+
+def test_tune_cache_load_skips_invalid_lines(nsf, tmp_path):
+    """nsf_tune_load keeps only lines that name a configuration the library
+    runs on their grid."""
+    base = ('{"arch": "gfx950", "nx": 48, "ny": 40, "nz": 36, "precision": 0, "variant": %d, '
+            '"block_x": 32, "block_y": %d, "zchunk": %d, "fuse": %d, "naive": 0, "gstore": %d, '
+            '"pt_rhs_per_s": 1e9, "parity_rel_err": 1e-14}')
+    lines = [base % (3, 16, 32, 1, 0),   # SN fused: valid
+             base % (7, 16, 32, 0, 0),   # no such algorithm
+             base % (3, 12, 32, 1, 0),   # tile height 12
+             base % (3, 16, 99, 1, 0),   # z-chunk beyond the grid
+             base % (2, 16, 32, 1, 0),   # SS cannot fuse
+             base % (2, 16, 32, 0, 4),   # in-plane store set on a 3D grid
+             base % (2, 16, 32, 0, 3)]   # SS, diagonal store set: valid
+    path = tmp_path / "cache.jsonl"
+    path.write_text("\n".join(lines) + "\n")
+    assert nsf.tune_load(str(path)) == 2
+    got = nsf.tune_get((48, 40, 36), "f64")
+    assert got["variant"] == "SS" and got["tune"]["gstore"] == 3

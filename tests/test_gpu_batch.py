@@ -26,8 +26,9 @@ def small_instances(count=6, seed=5):
     return W.batch_instances(count=count, seed=seed, sizes=(16, 24, 32, 40))
 
 
-def single(inst, precision, nsteps):
-    s = nsf.Solver(inst["shape"], inst["phys"], "SN", precision, tune={"fuse": 1})
+def single(inst, precision, nsteps, block_y=0):
+    s = nsf.Solver(inst["shape"], inst["phys"], "SN", precision,
+                   tune={"fuse": 1, "block_y": block_y})
     s.init(inst["tgv"])
     s.step(inst["dt"], nsteps)
     return s
@@ -106,6 +107,81 @@ def test_batch_full_ensemble_one_step():
         s = single(insts[i], "f64", 1)
         assert torch.equal(b.q[i], s.q), i
         del s
+    d = b.diagnostics()
+    assert np.all(d[:, 14] == 0)
+    b.close()
+
+
+def test_batch_real_ensemble_low_mach_against_oracle():
+    # instances of the 64-instance ensemble itself at its largest grids and
+    # lowest Mach numbers (where the double-precision floor is highest): the
+    # N = 96 and N = 128 instances of smallest Ma (0.055 and 0.107 for this
+    # seed), the instance of smallest Ma overall, and the N = 128 instance of
+    # largest Ma, two steps against the extended-precision oracle. Bars:
+    # 1e-10 on the state; on the two steps' increment q(2 dt) - q(0), 4x the
+    # oracle's own double-precision error on it (at least 1e-10)
+    ens = W.batch_instances()
+    def pick(n, key):
+        cand = [i for i in ens if i["shape"][0] == n]
+        return key(cand, key=lambda i: i["phys"]["Ma"])
+    lowest = min(ens, key=lambda i: i["phys"]["Ma"])
+    insts = [pick(96, min), pick(128, min), lowest, pick(128, max)]
+    print("case real ensemble", [(i["shape"][0], round(i["phys"]["Ma"], 4)) for i in insts],
+          flush=True)
+    assert insts[0]["phys"]["Ma"] < 0.06 and lowest["phys"]["Ma"] < 0.06
+    b = nsf.Batch(insts, "f64")
+    b.step(2)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        q0 = O.init(inst["shape"], inst["phys"], inst["tgv"], prec="ld")
+        ref = O.rk_step(q0, inst["phys"], inst["dt"], 2, prec="ld")
+        dbl = O.rk_step(q0.astype(np.float64), inst["phys"], inst["dt"], 2, prec="d")
+        got = b.q[i].cpu().numpy()
+        assert np.all(rel_err(got, ref) <= 1e-10), (i, rel_err(got, ref))
+        base = q0.astype(np.float64)
+        ref_inc = (ref - q0).astype(np.float64)
+        err = rel_err(got - base, ref_inc)
+        floor = rel_err(dbl - base, ref_inc)
+        assert np.all(err <= np.maximum(1e-10, 4 * floor)), (i, err, floor)
+        assert torch.equal(b.q[i], b.q_acc[i])
+    b.close()
+
+
+@pytest.mark.parametrize("variant,tune", [("SN", {"block_y": 8, "zchunk": 5}),
+                                          ("RA", None), ("RA", {"block_y": 8, "zchunk": 7})])
+def test_batch_variant_and_tuning_match_single(variant, tune):
+    # the batched RA stage and explicit tile knobs: each instance bitwise
+    # equal to the single-grid fused path of the same algorithm and tile
+    # height (the z-chunk does not change any value)
+    insts = small_instances(4, seed=21)
+    b = nsf.Batch(insts, "f64", variant=variant, tune=tune)
+    cfg = b.config()
+    by = (tune or {}).get("block_y", 0) or 16
+    assert cfg["variant"] == variant and cfg["tile_y"] == by
+    zc = (tune or {}).get("zchunk", 0)
+    if zc:
+        assert cfg["zchunk"] == [min(zc, i["shape"][2]) for i in insts]
+    b.step(2)
+    torch.cuda.synchronize()
+    for i, inst in enumerate(insts):
+        s = nsf.Solver(inst["shape"], inst["phys"], variant, "f64", tune={"fuse": 1, "block_y": by})
+        s.init(inst["tgv"])
+        s.step(inst["dt"], 2)
+        assert torch.equal(b.q[i], s.q), i
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_batch_autotune(precision):
+    # the batched-form search returns a parity-checked winner that
+    # nsf_batch_create_variant runs
+    insts = small_instances(6, seed=4)
+    best = nsf.batch_autotune(insts, precision, steps=2)
+    assert best["variant"] in ("SN", "RA") and best["tune"]["block_y"] in (8, 16)
+    assert best["pt_rhs_per_s"] > 0
+    b = nsf.Batch(insts, precision, variant=best["variant"], tune=best["tune"])
+    assert b.config()["tile_y"] == best["tune"]["block_y"]
+    b.step(1)
     d = b.diagnostics()
     assert np.all(d[:, 14] == 0)
     b.close()

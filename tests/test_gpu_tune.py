@@ -28,7 +28,7 @@ def test_autotune_choice_is_parity_gated_and_used_by_auto(tmp_path, precision):
     assert best["pt_rhs_per_s"] > 0 and best["parity_rel_err"] <= bar
     assert nsf.tune_get(shape, precision)["variant"] == best["variant"]
     lines = open(cache).read().strip().splitlines()
-    assert len(lines) == 1 and '"gfx950"' in lines[0]
+    assert len(lines) == 1 and '"gfx950"' in lines[0] and '"gstore"' in lines[0]
     assert nsf.tune_load(cache) == 1
     # AUTO runs exactly the recorded configuration
     tgv = W.tgv_pointwise(5, 1e-3)
@@ -81,6 +81,29 @@ def test_sn_rs_ra_parity(variant, shape, tune):
     err = rel_err(s.r.cpu().numpy(), ref)
     floor = rel_err(O.rhs(q.astype(np.float64), PHYS, prec="d"), ref)
     assert np.all(err <= np.maximum(1e-12, 4 * floor)), err
+
+
+@pytest.mark.parametrize("variant", ["SS", "RS"])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 16, 16), (40, 36, 50), (70, 11, 9), (5, 6, 7)])
+@pytest.mark.parametrize("tune", [{"gstore": 3}, {"gstore": 3, "block_y": 8, "zchunk": 7},
+                                  {"gstore": 9, "block_y": 16, "zchunk": 5}])
+def test_store_set_parity(variant, precision, shape, tune):
+    # the stored-gradient algorithms with the diagonal store set (the other
+    # six gradients formed in the kernel) and the full set
+    print(f"case store set {variant} {precision} {shape} {tune}", flush=True)
+    q = O.init(shape, PHYS, W.tgv_pointwise(3, 1e-3), prec="ld")
+    qin = q.astype(np.float64 if precision == "f64" else np.float32)
+    ref = O.rhs(qin.astype(np.longdouble), PHYS, prec="ld")
+    s = nsf.Solver(shape, PHYS, variant, precision, tune=tune)
+    s.q.copy_(torch.from_numpy(qin))
+    s.rhs()
+    err = rel_err(s.r.cpu().numpy().astype(np.float64), ref)
+    if precision == "f64":
+        bar = np.maximum(1e-12, 4 * rel_err(O.rhs(q.astype(np.float64), PHYS, prec="d"), ref))
+    else:
+        bar = 4 * rel_err(ref, O.rhs(q, PHYS, prec="ld"))
+    assert np.all(err <= bar), (err, bar)
 
 
 def test_recompute_and_thread_local_forms_round_differently():
