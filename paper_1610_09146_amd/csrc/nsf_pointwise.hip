@@ -187,12 +187,21 @@ void launch_prims_bl(const Dims& d, const Coef<T>& c, const T* q, T* prim, hipSt
     hipLaunchKernelGGL(k_prims_bl_t<T>, g, dim3(kBlock), 0, s, d, c, q, prim);
 }
 
+// The five fields of a state can hold more than 2^32 elements (a 1024^3
+// grid has 5 * 2^30), more work items than one dispatch can address (its
+// grid size is 32-bit), so the update is issued in launches of at most 2^31
+// elements.
 template <typename T>
 void launch_update(const Dims& d, const StageCoef& sc, const T* r, T* q, double* qacc,
                    hipStream_t s) {
     TimerScope ts("update", s);
     const size_t n5 = 5 * d.npts;
-    hipLaunchKernelGGL(k_update<T>, dim3(grid_for(n5, kBlock)), dim3(kBlock), 0, s, n5, sc, r, q, qacc);
+    constexpr size_t kPart = (size_t)1 << 31;
+    for (size_t base = 0; base < n5; base += kPart) {
+        const size_t m = n5 - base < kPart ? n5 - base : kPart;
+        hipLaunchKernelGGL(k_update<T>, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s, m, sc,
+                           r + base, q + base, qacc + base);
+    }
 }
 
 template <typename T>
@@ -204,10 +213,13 @@ void launch_product(const Dims& d, const T* f, const T* g, T* out, hipStream_t s
 void launch_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     TimerScope ts("copy", s);
     const size_t n16 = bytes / 16;
-    if (n16) {
-        // one lane per element: up to 2^31 - 1 blocks, i.e. 8 TiB
-        hipLaunchKernelGGL(k_copy16, dim3(grid_for(n16, kBlock)), dim3(kBlock), 0, s, n16,
-                           (const v4u*)src, (v4u*)dst);
+    // one lane per element, in launches of at most 2^31 elements (a dispatch
+    // addresses fewer than 2^32 work items)
+    constexpr size_t kPart = (size_t)1 << 31;
+    for (size_t base = 0; base < n16; base += kPart) {
+        const size_t m = n16 - base < kPart ? n16 - base : kPart;
+        hipLaunchKernelGGL(k_copy16, dim3(grid_for(m, kBlock)), dim3(kBlock), 0, s, m,
+                           (const v4u*)src + base, (v4u*)dst + base);
     }
     const size_t tail = bytes - n16 * 16;
     if (tail)

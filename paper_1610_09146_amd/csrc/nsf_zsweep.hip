@@ -1168,13 +1168,24 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             const T* Gs = A.grad;
             const size_t pz = poff(z);
             auto gat = [&](int comp, size_t off) { return Gs[comp * n + off]; };
+            // (the full store set keeps the plain loop: written with the
+            // store-set test, its compiled schedule spilled, +14% at 512^3)
+            if constexpr (GM == kGradAll) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
+                for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b)
-                    if (gstored(a, b))
-                        ac.G[a][b] = a == b ? gat(gslot(a, b), pz + col)
-                                            : stream_load(Gs + gslot(a, b) * n + pz + col);
+                    for (int b = 0; b < 3; ++b)
+                        ac.G[a][b] = a == b ? gat(3 * a + b, pz + col)
+                                            : stream_load(Gs + (3 * a + b) * n + pz + col);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int b = 0; b < 3; ++b)
+                        if (gstored(a, b))
+                            ac.G[a][b] = a == b ? gat(gslot(a, b), pz + col)
+                                                : stream_load(Gs + gslot(a, b) * n + pz + col);
+            }
             auto dxg = [&](int comp) {
                 return D1(gat(comp, pz + xnb[0]), gat(comp, pz + xnb[1]), gat(comp, pz + xnb[2]),
                           gat(comp, pz + xnb[3]), k.a1[0], k.a2[0]);
@@ -1185,8 +1196,13 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             };
             // (a store set without G_zz belongs to a single-plane grid, where
             // every z difference, hence G_zz, is zero)
-            cross[0] = dxg(gslot(1, 1)) + (gstored(2, 2) ? dxg(gslot(2, 2)) : T(0));
-            cross[1] = dyg(gslot(0, 0)) + (gstored(2, 2) ? dyg(gslot(2, 2)) : T(0));
+            if constexpr (GM == kGradAll) {
+                cross[0] = dxg(4) + dxg(8);
+                cross[1] = dyg(0) + dyg(8);
+            } else {
+                cross[0] = dxg(gslot(1, 1)) + (gstored(2, 2) ? dxg(gslot(2, 2)) : T(0));
+                cross[1] = dyg(gslot(0, 0)) + (gstored(2, 2) ? dyg(gslot(2, 2)) : T(0));
+            }
             cross[2] = D1(Xs[0], Xs[1], Xs[3], Xs[4], k.a1[2], k.a2[2]) +
                        D1(Xw[0], Xw[1], Xw[3], Xw[4], k.a1[2], k.a2[2]);
         } else {
