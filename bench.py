@@ -57,6 +57,7 @@ FAMILY_BYTES = {
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
     "ss_grad": (96, 48),          # u, v, w -> 9 gradients
     "ss_zsweep": (192, 96),       # q, prims, 9 gradients -> r
+    "ss_fused": (272, 176),       # fused SS: q, prims, 9 gradients, q_acc -> q_next, q_acc
     "bl_deriv": (16, 8),          # one field -> one derivative
     "bl_product": (24, 12),       # two fields -> one product
     "bl_assemble": (584, 292),    # 60 derivatives, q, u -> r
@@ -109,6 +110,8 @@ def families(variant, tune):
         return ["prims", f"{k}_zsweep", "update", "diag"]
     if tune and tune.get("naive"):
         return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
+    if variant == "SS" and tune and tune.get("fuse"):
+        return ["prims", "ss_grad", "ss_fused", "diag"]
     return ["prims", "ss_grad", "rs_zsweep" if variant == "RS" else "ss_zsweep", "update", "diag"]
 
 
@@ -472,7 +475,7 @@ def main() -> int:
         main_variant, main_tune = tuned[args.precision]["variant"], tuned[args.precision]["tune"]
     else:
         main_variant = args.variant
-        main_tune = {"fuse": args.fuse if args.variant in ("RA", "SN") else 0,
+        main_tune = {"fuse": args.fuse if args.variant in ("RA", "SN", "SS") else 0,
                      "block_y": args.block_y, "zchunk": args.zchunk}
     log(f"main: {main_variant} {main_tune} {args.precision} n={n} steps={args.steps}")
     main_res = run_variant(nsf, torch, W, n, main_variant, args.precision, args.steps, args.warmup,
@@ -482,6 +485,7 @@ def main() -> int:
     if not args.no_extras:
         for name, v, prec, k, tune in (("BL_f64", "BL", "f64", 3, None),
                                        ("SS_f64", "SS", "f64", 5, None),
+                                       ("SS_f64_fused", "SS", "f64", 5, {"fuse": 1}),
                                        ("RS_f64", "RS", "f64", 5, None),
                                        ("SN_f64_stored_prims", "SN", "f64", 5, None),
                                        ("RA_f64_stored_prims", "RA", "f64", 5, None),
@@ -494,14 +498,15 @@ def main() -> int:
             r["roofline"] = roofline_of(r, prec)
             extras[name] = r
         # the paper's Table 1 on one MI355X: the five algorithms in the
-        # paper's form (stored primitives, separate update) and the fused RA
+        # paper's form (stored primitives, separate update) and the fused SS, RA
         # and SN, FP64, at 64^3, 128^3 and 256^3, pointwise +-1e-3
         # perturbation (seed 1610), 100 steps
         table = []
         for nt in (64, 128, 256):
             for name, v, tune in (("BL", "BL", None), ("RA", "RA", None), ("RS", "RS", None),
                                   ("SN", "SN", None), ("SS", "SS", None),
-                                  ("RA_fused", "RA", {"fuse": 1}), ("SN_fused", "SN", {"fuse": 1})):
+                                  ("RA_fused", "RA", {"fuse": 1}), ("SN_fused", "SN", {"fuse": 1}),
+                                  ("SS_fused", "SS", {"fuse": 1})):
                 log(f"extra: {nt}^3 {name}")
                 r = run_variant(nsf, torch, W, nt, v, "f64", 100, 1, tune=tune,
                                 tgv=W.tgv_pointwise(1610, 1e-3))

@@ -75,7 +75,7 @@ typedef enum {
  *   NSF_SS  store some: the nine velocity gradients stored as in RS, the
  *           other derivatives formed once into thread-local values.
  * In every algorithm the primitive variables are a stored array and the RK
- * update its own kernel (the paper's structure); RA and SN also have the
+ * update its own kernel (the paper's structure); RA, SN and SS also have a
  * fused form (nsf_tuning.fuse). */
 typedef enum { NSF_BL = 0, NSF_RA = 1, NSF_SS = 2, NSF_SN = 3, NSF_RS = 4, NSF_AUTO = 5 } nsf_variant;
 /* NSF_AUTO: the algorithm and tuning that nsf_autotune (or nsf_tune_load)
@@ -120,10 +120,13 @@ typedef struct {
  *   block_x, block_y: x-y tile of the z-sweeping kernels: block_x is 32,
  *         block_y 8 or 16 (0 = default);
  *   zchunk: planes marched per workgroup by the z-sweeping kernels (0 = default);
- *   fuse: RA/SN only. 0 = primitives stored by their own kernel and the RK
- *         update a separate kernel, as in the paper; 1 = primitives
- *         recomputed inside the residual tile and the RK update fused into
- *         the residual kernel (needs the ping-pong copy of q in `work`).
+ *   fuse: RA/SN/SS (ignored elsewhere). 0 = primitives stored by their
+ *         own kernel and the RK update a separate kernel, as in the paper;
+ *         1 = the RK update applied in the residual kernel's epilogue, and
+ *         in RA and SN the primitives recomputed inside the residual tile
+ *         (SS keeps its stored primitives and gradients). nsf_rk_step then
+ *         rotates the state through a copy of q in `work` (and, in SS,
+ *         through r); nsf_rhs is unchanged.
  *   naive: 1 = use the untiled per-point kernels (reference GPU path): one
  *         kernel per store set, so RA and SN run the same untiled kernel,
  *         and so do RS and SS;
@@ -186,9 +189,9 @@ int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precis
  * 2s+1 receive the grid means of rho|u|^2/2 and rho|omega|^2/2 (omega =
  * curl u by the fourth-order first difference) of the state at the start of
  * step s, the quantities of out[0] and out[1] of nsf_diagnostics. In the
- * fused RA form the sums are formed inside the first stage's residual
- * kernel from the values it already holds; otherwise a diagnostics pass
- * runs before every step. NSF_EINVAL for a NULL or misaligned monitor.
+ * fused SN and RA forms the sums are formed inside the first stage's
+ * residual kernel from the values it already holds; otherwise a
+ * diagnostics pass runs before every step. NSF_EINVAL for a NULL or misaligned monitor.
  * Asynchronous. */
 int nsf_rk_step_monitored(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
                           const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
@@ -232,26 +235,33 @@ int nsf_diagnostics_noalloc(const nsf_grid *g, const nsf_phys *phys, int precisi
  * single-plane grid the four in-plane ones or all nine), whether the
  * derivatives not stored are thread-local values (SN, SS) or formed at each
  * use (RA, RS), the primitives stored or recomputed in the tile with the RK
- * update fused (SN, RA), and BL, crossed with the tile height and z-chunk of
+ * update fused (SN, RA), the RK update fused into the stored-gradient
+ * residual (SS), and BL, crossed with the tile height and z-chunk of
  * the z-sweeping kernels. Every candidate is first checked, per field,
  * against a reference residual on a seeded perturbed Taylor-Green state of
  * the same grid: in double precision the untiled kernels', at 1e-10
  * relative max-norm difference; in single precision the double-precision
  * untiled residual of the same single-precision state, within 4 times the
  * change that rounding the state to single precision makes to that
- * residual. Only passing candidates are timed (`steps` RK steps each, from
+ * residual. The residual checked is the one nsf_rhs forms, which for the
+ * fused forms is their algorithm's separate-update kernel; a fused
+ * candidate must also reproduce one RK step of that path from the same
+ * state (step: half the acoustic CFL limit of the finest axis), per field
+ * relative to the step's increment, at the residual bar (twice it in single
+ * precision) or 64 units in the last place of the state, whichever is
+ * larger. Only passing candidates are timed (`steps` RK steps each, from
  * the same initial state and accumulator). Candidates within 2% of the
  * fastest count as ties, resolved toward the default tuning and then the
  * larger z-chunk. The winner is recorded for NSF_AUTO and, if cache_path
  * is not NULL, appended as one JSON line to that file. Synchronous.
- * Allocates its own device buffers (four to six states and the largest
+ * Allocates its own device buffers (five to seven states and the largest
  * candidate's work) for the duration of the call. */
 #define NSF_TUNE_QUICK 1 /* skip BL and the untiled kernels */
 typedef struct {
     int32_t variant;
     nsf_tuning tune;
     double pt_rhs_per_s;   /* measured grid-point residual evaluations/s */
-    double parity_rel_err; /* worst per-field relative difference */
+    double parity_rel_err; /* worst per-field relative residual difference */
 } nsf_tune_result;
 
 int nsf_autotune(const nsf_grid *g, const nsf_phys *phys, int precision, int flags, int32_t steps,

@@ -119,7 +119,8 @@ struct Layout {
     size_t prim = 0, deriv = 0, prod = 0, qb = 0, qc = 0, mon = 0, diag_partial = 0,
            diag_out = 0, total = 0;
     int nderiv = 0;
-    bool fused = false;
+    bool fused = false;     // fused SN / RA stages
+    bool ss_fused = false;  // fused SS stages
 };
 
 int zchunk_of(const Dims& d, const nsf_tuning* tune) {
@@ -162,6 +163,11 @@ bool wants_fused(int variant, const nsf_tuning* tune) {
     return (variant == NSF_RA || variant == NSF_SN) && tune && tune->fuse && !tune->naive;
 }
 
+// SS with the stage update applied in the residual kernel's epilogue
+bool wants_ss_fused(int variant, const nsf_tuning* tune) {
+    return variant == NSF_SS && tune && tune->fuse && !tune->naive;
+}
+
 bool is_variant(int v) { return v >= NSF_BL && v <= NSF_AUTO; }
 
 // NSF_AUTO -> the recorded (or default) algorithm and tuning; `store`
@@ -193,6 +199,7 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     const size_t es = precision == NSF_F32 ? 4 : 8;
     Layout L;
     L.fused = wants_fused(variant, tune);
+    L.ss_fused = wants_ss_fused(variant, tune);
     size_t off = 0;
     L.prim = off;
     off = align_up(off + 5 * d.npts * es);
@@ -201,12 +208,13 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     off = align_up(off + (size_t)L.nderiv * d.npts * es);
     L.prod = off;
     off = align_up(off + (variant == NSF_BL ? d.npts * es : 0));
-    // fused RA stages rotate the state through q -> qb -> qc -> q. qb shares
-    // the primitive region: nsf_rhs uses the primitives and nsf_rk_step the
-    // rotating state, never both in one call.
+    // fused SN / RA stages rotate the state through q -> qb -> qc -> q. qb
+    // shares the primitive region: nsf_rhs uses the primitives and
+    // nsf_rk_step the rotating state, never both in one call. Fused SS
+    // stages read the primitives, and rotate through q -> r -> qc -> q.
     L.qb = L.fused ? L.prim : off;
     L.qc = off;
-    off = align_up(off + (L.fused ? 5 * d.npts * es : 0));
+    off = align_up(off + (L.fused || L.ss_fused ? 5 * d.npts * es : 0));
     // per-tile (KE, enstrophy) sums of the monitored first stage
     L.mon = off;
     off = align_up(off + (L.fused ? 2 * sizeof(double) *
@@ -370,6 +378,36 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
         return check_hip("rk_step launch");
     }
     const Coef<double> cd = make_coef<double>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
+    if (L.ss_fused) {
+        const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
+        T* prim = (T*)(work + L.prim);
+        T* grad = (T*)(work + L.deriv);
+        T* qc = (T*)(work + L.qc);
+        T* in[3] = {q, r, qc};
+        T* out[3] = {r, qc, q};
+        const int gm = gmask_of(d, variant, tune);
+        const int zc = zchunk_of(d, tune);
+        const int ty = tile_y_of(d, tune, sizeof(T));
+        for (int step = 0; step < nsteps; ++step) {
+            if (monitor) {
+                double* dout = (double*)(work + L.diag_out);
+                launch_diag<T>(d, cd, q, (double*)(work + L.diag_partial), dout, s);
+                hipError_t e = hipMemcpyAsync(monitor + 2 * step, dout, 2 * sizeof(double),
+                                              hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return fail(NSF_EHIP, "monitor copy: %s", hipGetErrorString(e));
+            }
+            for (int st = 0; st < 3; ++st) {
+                StageCoef sc;
+                sc.a_dt = st < 2 ? A[st] * dt : 0.0;
+                sc.b_dt = B[st] * dt;
+                sc.last = st == 2;
+                launch_prims<T>(d, c, in[st], prim, s);
+                launch_ss_grad<T>(d, c, prim, grad, gm, s);
+                launch_ss_fused<T>(d, c, in[st], prim, grad, out[st], qacc, sc, zc, ty, s, gm);
+            }
+        }
+        return check_hip("rk_step launch");
+    }
     for (int step = 0; step < nsteps; ++step) {
         if (monitor) {
             // the diagnostics pass writes NDIAG means; KE and enstrophy lead
@@ -593,7 +631,7 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ra_fused_mon,"
     "ra_fused_first,ra_fused_last,sn_zsweep,sn_fused,sn_fused_mon,sn_fused_first,sn_fused_last,"
-    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,rs_zsweep,diag,copy,ra_batch,batch_step";
+    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,ss_fused,rs_zsweep,diag,copy,ra_batch,batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

@@ -153,6 +153,14 @@ template <typename T>
 void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
                       T* r, int zchunk, int tile_y, hipStream_t s, bool recompute,
                       int gmask = kGradAll);
+// Fused SS stage: the stored-gradient residual of q (stored primitives and
+// gradients as launch_ss_zsweep) with the stage update applied in its
+// epilogue, qout = q_acc + a dt R (b dt in the last stage), q_acc += b dt R;
+// qout must not overlap q.
+template <typename T>
+void launch_ss_fused(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
+                     T* qout, double* qacc, const StageCoef& sc, int zchunk, int tile_y,
+                     hipStream_t s, int gmask);
 // SS gradient loop: the store set's G_ab = D_b u_a into arrays (z-marching tiles).
 template <typename T>
 void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int gmask,

@@ -66,6 +66,37 @@ __global__ void k_maxdiff(size_t n, const void* a, int a_f32, const void* b, int
     }
 }
 
+// max over points of |a - b|, |b - base| and |b|, per field (double fields)
+__global__ void k_incdiff(size_t n, const double* a, const double* b, const double* base,
+                          double* out) {
+    __shared__ double sd[256], si[256], sb[256];
+    double md = 0.0, mi = 0.0, mb = 0.0;
+    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+        const double dd = fabs(a[e] - b[e]);
+        md = (dd > md || dd != dd) ? dd : md;
+        mi = fmax(mi, fabs(b[e] - base[e]));
+        mb = fmax(mb, fabs(b[e]));
+    }
+    sd[threadIdx.x] = md;
+    si[threadIdx.x] = mi;
+    sb[threadIdx.x] = mb;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const double o = sd[threadIdx.x + w];
+            sd[threadIdx.x] = (o > sd[threadIdx.x] || o != o) ? o : sd[threadIdx.x];
+            si[threadIdx.x] = fmax(si[threadIdx.x], si[threadIdx.x + w]);
+            sb[threadIdx.x] = fmax(sb[threadIdx.x], sb[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[3 * blockIdx.x] = sd[0];
+        out[3 * blockIdx.x + 1] = si[0];
+        out[3 * blockIdx.x + 2] = sb[0];
+    }
+}
+
 // double copy of a float state
 __global__ void k_widen(size_t n, const float* a, double* b) {
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256)
@@ -94,6 +125,35 @@ int rel_diff(const Dims& d, const void* a, bool a_f32, const void* b, bool b_f32
             mr = std::max(mr, host[2 * i + 1]);
         }
         rel[f] = mr > 0 ? md / mr : md;
+    }
+    return NSF_OK;
+}
+
+// Difference of two double states a and b taken one step from `base`,
+// relative to b's increment, per field: rel[f] = ||a_f - b_f|| / ||b_f -
+// base_f||; ulp[f] = 2^-52 ||b_f|| / ||b_f - base_f||, the size of one unit
+// in the last place of the state in those units (the floor of the
+// comparison, since an increment is formed by adding to the state).
+int inc_diff(const Dims& d, const double* a, const double* b, const double* base,
+             double* partial, hipStream_t s, double rel[5], double ulp[5]) {
+    std::vector<double> host(3 * kDiffBlocks);
+    for (int f = 0; f < 5; ++f) {
+        const size_t o = f * d.npts;
+        hipLaunchKernelGGL(k_incdiff, dim3(kDiffBlocks), dim3(256), 0, s, d.npts, a + o, b + o,
+                           base + o, partial);
+        hipError_t e = hipMemcpyAsync(host.data(), partial, host.size() * sizeof(double),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return tfail(NSF_EHIP, hipGetErrorString(e));
+        double md = 0.0, mi = 0.0, mb = 0.0;
+        for (int i = 0; i < kDiffBlocks; ++i) {
+            const double x = host[3 * i];
+            md = (x > md || x != x) ? x : md;
+            mi = std::max(mi, host[3 * i + 1]);
+            mb = std::max(mb, host[3 * i + 2]);
+        }
+        rel[f] = mi > 0 ? md / mi : md;
+        ulp[f] = mi > 0 ? std::ldexp(mb, -52) / mi : 0.0;
     }
     return NSF_OK;
 }
@@ -127,6 +187,7 @@ std::vector<nsf_tune_result> candidates(const nsf_grid* g, int flags) {
         add(NSF_RA, by, zd, 0, 0);
         for (int gs : gsets) {
             add(NSF_SS, by, zd, 0, 0, gs);
+            add(NSF_SS, by, zd, 1, 0, gs);
             add(NSF_RS, by, zd, 0, 0, gs);
         }
     }
@@ -182,7 +243,7 @@ bool valid_entry(const nsf_grid& g, int precision, const nsf_tune_result& r) {
     if (t.zchunk < 0 || t.zchunk > g.nz) return false;
     if ((t.fuse != 0 && t.fuse != 1) || (t.naive != 0 && t.naive != 1)) return false;
     if (t.fuse && t.naive) return false;
-    if (t.fuse && r.variant != NSF_RA && r.variant != NSF_SN) return false;
+    if (t.fuse && r.variant != NSF_RA && r.variant != NSF_SN && r.variant != NSF_SS) return false;
     if (t.gstore != 0 && t.gstore != 3 && t.gstore != 4 && t.gstore != 9) return false;
     if (t.gstore != 0 && r.variant != NSF_SS && r.variant != NSF_RS) return false;
     if (t.gstore == 4 && g.nz != 1) return false;
@@ -245,7 +306,7 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     // double state and its residual
     void *q0 = nullptr, *q = nullptr, *r = nullptr, *work = nullptr;
     double *qacc0 = nullptr, *qacc = nullptr, *rref = nullptr, *partial = nullptr;
-    double *q64 = nullptr, *r64 = nullptr;
+    double *q64 = nullptr, *r64 = nullptr, *qstep = nullptr;
     hipError_t e = hipMalloc(&q0, fb);
     if (e == hipSuccess) e = hipMalloc(&q, fb);
     if (e == hipSuccess) e = hipMalloc(&r, fb);
@@ -253,7 +314,8 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     if (e == hipSuccess) e = hipMalloc((void**)&qacc, db);
     if (e == hipSuccess) e = hipMalloc((void**)&rref, db);
     if (e == hipSuccess) e = hipMalloc(&work, wmax);
-    if (e == hipSuccess) e = hipMalloc((void**)&partial, 2 * kDiffBlocks * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&partial, 3 * kDiffBlocks * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&qstep, db);
     if (e == hipSuccess && f32) e = hipMalloc((void**)&q64, db);
     if (e == hipSuccess && f32) e = hipMalloc((void**)&r64, db);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -261,7 +323,7 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     if (e == hipSuccess) e = hipEventCreate(&t1);
     auto cleanup = [&]() {
         for (void* p : {q0, q, r, work, (void*)qacc0, (void*)qacc, (void*)rref, (void*)partial,
-                        (void*)q64, (void*)r64})
+                        (void*)q64, (void*)r64, (void*)qstep})
             if (p) (void)hipFree(p);
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
@@ -298,6 +360,16 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
         for (int f = 0; f < 5; ++f) bar[f] = 4.0 * rnd[f];
     }
     const double dt = 1e-4;
+    // step of the fused-form check: half the acoustic CFL limit of the
+    // finest axis (any step compares two implementations of the same step;
+    // a large one keeps the increment well above the state's last place)
+    const int nmax = std::max(g->nx, std::max(g->ny, g->nz));
+    const double dt_gate = 0.5 * (2.0 * M_PI / nmax) / (1.0 + 1.0 / phys->Ma);
+    auto reset = [&]() {
+        hipError_t x = hipMemcpyAsync(q, q0, fb, hipMemcpyDeviceToDevice, s);
+        if (x == hipSuccess) x = hipMemcpyAsync(qacc, qacc0, db, hipMemcpyDeviceToDevice, s);
+        return x == hipSuccess ? NSF_OK : tfail(NSF_EHIP, hipGetErrorString(x));
+    };
     nsf_tune_result win;
     std::memset(&win, 0, sizeof win);
     win.variant = -1;
@@ -313,6 +385,27 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
             worst = std::max(worst, err[f] / bar[f]);
         }
         c.parity_rel_err = *std::max_element(err, err + 5);
+        if (pass && c.tune.fuse) {
+            // The fused forms' stage kernels are not what nsf_rhs runs (it
+            // runs the same algorithm's separate-update residual, checked
+            // above): one fused step is checked against one step of that
+            // path from the same state, relative to the step's increment, at
+            // the residual bar (twice it in single precision, where each of
+            // the two residuals lies within the bar of the reference), and
+            // never below 64 units in the last place of the state.
+            nsf_tuning u = c.tune;
+            u.fuse = 0;
+            if ((rc = reset())) break;
+            if ((rc = nsf_rk_step(g, phys, c.variant, precision, &u, dt_gate, 1, q, qacc, r, work, wmax, stream))) break;
+            e = hipMemcpyAsync(qstep, qacc, db, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) { rc = tfail(NSF_EHIP, hipGetErrorString(e)); break; }
+            if ((rc = reset())) break;
+            if ((rc = nsf_rk_step(g, phys, c.variant, precision, &c.tune, dt_gate, 1, q, qacc, r, work, wmax, stream))) break;
+            double srel[5], sulp[5];
+            if ((rc = inc_diff(d, qacc, qstep, qacc0, partial, s, srel, sulp))) break;
+            for (int f = 0; f < 5; ++f)
+                pass = pass && srel[f] <= std::max((f32 ? 2.0 : 1.0) * bar[f], 64.0 * sulp[f]);
+        }
         if (!pass) {
             c.pt_rhs_per_s = 0.0;
             continue;
@@ -320,9 +413,7 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
         (void)worst;
         // timing: from the initial state and accumulator, one untimed step,
         // then `steps` steps between events
-        e = hipMemcpyAsync(q, q0, fb, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(qacc, qacc0, db, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) { rc = tfail(NSF_EHIP, hipGetErrorString(e)); break; }
+        if ((rc = reset())) break;
         if ((rc = nsf_rk_step(g, phys, c.variant, precision, &c.tune, dt, 1, q, qacc, r, work, wmax, stream))) break;
         e = hipEventRecord(t0, s);
         if (e == hipSuccess &&

@@ -611,17 +611,24 @@ constexpr int ring_slots() {
     return FUSED && d_ring<T, TY, SS, RC>() ? 4 : 5;
 }
 
-// Whether the fused form keeps a per-thread halo ring in LDS (each halo
-// point fetched once per plane: its velocity is taken at the leading plane
-// and its plane fields are parked until it is the centre plane) or fetches
-// every halo point twice per plane from the L2. Double-precision 32 x 8
-// tiles drop the ring: without its LDS two workgroups fit on a CU.
+// Whether a tile keeps a per-thread halo ring in LDS: each halo point is
+// fetched once per plane, with the leading plane z+2 (the plane the
+// neighbouring tile fetches as interior in the same iteration, so the
+// halo's cache lines are still in the L2); its velocity goes to the ring at
+// once and its plane fields are parked until it is the centre plane.
+// Without the ring, the fused form fetches every halo point twice per plane,
+// and the stored-gradient form fetches the plane fields of plane z+1, two
+// planes after the neighbouring tile did: its nineteen fields per point
+// fill the L2 within those two planes, so each halo row came from HBM again
+// (the x-halo columns as whole 128-byte lines: 1.66x the algorithmic reads
+// of that kernel at 512^3). Double-precision 32 x 8 tiles drop the ring:
+// without its LDS two workgroups fit on a CU.
 #ifndef NSF_F64_Y8_HALO_RING
 #define NSF_F64_Y8_HALO_RING 0
 #endif
-template <typename T, int TY, bool FUSED, bool MON = false>
+template <typename T, int TY, bool FUSED, bool MON = false, bool SS = false>
 constexpr bool halo_ring() {
-    return FUSED && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
+    return (FUSED || SS) && (sizeof(T) == 4 || TY != 8 || NSF_F64_Y8_HALO_RING);
 }
 
 // Plane fields kept in LDS with their halo: rho, E, p, T (momentum at a
@@ -639,16 +646,19 @@ struct PlaneLds {
     static constexpr int kFields = SS ? 7 : kPF;
     static constexpr int kBuffers = SS ? 1 : 2;
 };
+// plane fields a halo-ring slot parks per halo point: the plane buffer's
+template <bool SS>
+constexpr int halo_fields() { return PlaneLds<SS>::kFields; }
 
 // One tile (x-y tile tix, tiy; z-chunk tiz, packed as t) of one grid. sP
-// holds 2 * kPF * NPL values (the plane fields of two planes), sV
-// ring_slots * 3 * NPL (the velocity ring). In the fused form sH holds
-// 2 * kPF * NHALO values: the plane fields of the raw values each thread
-// loaded at its halo point, parked until the point's plane is the centre
-// plane (a per-thread ring in LDS, so every halo point is fetched once per
-// plane, in the same iteration in which the neighbouring tile fetches it as
-// interior; two slots, since each thread reads plane z's entry before
-// parking plane z+2's in the same slot). With the D ring, sD holds
+// holds kBuffers * kFields * NPL values (the plane fields), sV
+// ring_slots * 3 * NPL (the velocity ring). With the halo ring sH holds
+// 2 * halo_fields * NHALO values: the plane fields of the raw values each
+// thread loaded at its halo point, parked until the point's plane is the
+// centre plane (a per-thread ring in LDS, so every halo point is fetched
+// once per plane, in the same iteration in which the neighbouring tile
+// fetches it as interior; two slots, since each thread reads plane z's
+// entry before parking plane z+2's in the same slot). With the D ring, sD holds
 // 3 * DSZ values. Ends with a barrier, so the caller may reuse the LDS for
 // another tile right away.
 template <typename T, int TX, int TY, bool FUSED, bool SS = false, bool MON = false,
@@ -657,9 +667,15 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                                             T* __restrict__ sV, T* __restrict__ sH,
                                             T* __restrict__ sD,
                                             double2* __restrict__ sM = nullptr) {
-    static_assert(!(FUSED && SS), "the stored-gradient form reads stored primitives");
+    // FUSED: the stage update is applied in the epilogue (q_out, q_acc
+    // instead of r). RP: the primitives are recomputed from q in the tile;
+    // the stored-gradient forms read them from their stored arrays, fused or
+    // not.
+    constexpr bool RP = FUSED && !SS;
+    static_assert(!(FUSED && SS && (MON || RC)), "the fused stored-gradient stage is SS, unmonitored");
     static_assert(!MON || FUSED, "the monitor is part of the fused stage");
-    constexpr bool HR = halo_ring<T, TY, FUSED, MON>();
+    constexpr bool HR = halo_ring<T, TY, FUSED, MON, SS>();
+    constexpr int HF = halo_fields<SS>();
     // Lean form of the fused stage: no branch between the prefetch and the
     // next iteration. Halo prefetches run on every lane and the epilogue uses
     // buffer accesses that drop the lanes outside the grid. With a branch
@@ -668,7 +684,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // waits for this plane's stores. (The monitored stage keeps the branch
     // where its sums would not fit the registers without it: in single
     // precision and in the 8-row double-precision tile.)
-    constexpr bool kLean = FUSED && !(MON && (sizeof(T) == 4 || TY == 8));
+    constexpr bool kLean = RP && !(MON && (sizeof(T) == 4 || TY == 8));
     // Momenta in the z fold: every recomputed-derivative form takes rho * u
     // from the queue and the velocity ring, as the x and y folds do, instead
     // of holding the conserved momenta of five planes in registers (this is
@@ -782,9 +798,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     T uvw[5][3];
 #pragma unroll
     for (int s = 0; s < 5; ++s) {
-        Raw<T, FUSED> raw;
-        load_raw<T, FUSED>(raw, A.q, A.prim, n, poff(z0 - 2 + s) + col);
-        Qz[s] = finish<T, FUSED>(raw, k, uvw[s]);
+        Raw<T, RP> raw;
+        load_raw<T, RP>(raw, A.q, A.prim, n, poff(z0 - 2 + s) + col);
+        Qz[s] = finish<T, RP>(raw, k, uvw[s]);
     }
     T unew[3] = {uvw[4][0], uvw[4][1], uvw[4][2]};  // own velocity of plane z+2
 
@@ -830,16 +846,33 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         yw = D1u(W[ownV - 2 * RSV], W[ownV - RSV], W[ownV + RSV], W[ownV + 2 * RSV]);
     };
 
-    // per-thread halo ring (fused form): slot of plane zz, plane field f
-    // (rho, E, p, T: the values the plane buffer takes at that halo point)
+    // per-thread halo ring: slot of plane zz, plane field f (the values the
+    // plane buffer takes at that halo point: rho, E, p, T, and in the
+    // stored-gradient form the momenta after them)
     auto hring = [&](int zz, int f, int h) -> T& {
-        return sH[(pmod(zz, 2) * kPF + f) * NHALO + tid + h * NT];
+        return sH[(pmod(zz, 2) * HF + f) * NHALO + tid + h * NT];
     };
     auto park = [&](int zz, int h, const T f7[7]) {
         hring(zz, 0, h) = f7[0];
         hring(zz, 1, h) = f7[4];
         hring(zz, 2, h) = f7[5];
         hring(zz, 3, h) = f7[6];
+        if constexpr (HF == 7) {
+            hring(zz, 4, h) = f7[1];
+            hring(zz, 5, h) = f7[2];
+            hring(zz, 6, h) = f7[3];
+        }
+    };
+    auto unpark = [&](int zz, int h, T f7[7]) {
+        f7[0] = hring(zz, 0, h);
+        f7[4] = hring(zz, 1, h);
+        f7[5] = hring(zz, 2, h);
+        f7[6] = hring(zz, 3, h);
+        if constexpr (HF == 7) {
+            f7[1] = hring(zz, 4, h);
+            f7[2] = hring(zz, 5, h);
+            f7[3] = hring(zz, 6, h);
+        }
     };
 
     // preamble: ring planes z0-2 .. z0+1 and their queued in-plane derivatives
@@ -854,9 +887,9 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         for (int h = 0; h < HPT; ++h)
             if (hval[h]) {
                 T u, v, w;
-                if constexpr (FUSED) {
-                    RawP<T, FUSED> rp;
-                    load_rawp<T, FUSED>(rp, A.q, A.prim, n, poff(zz) + hcol[h]);
+                if constexpr (RP) {
+                    RawP<T, RP> rp;
+                    load_rawp<T, RP>(rp, A.q, A.prim, n, poff(zz) + hcol[h]);
                     const T ir = fast_rcp(rp.a[0]);
                     u = rp.a[1] * ir;
                     v = rp.a[2] * ir;
@@ -864,13 +897,21 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     if constexpr (HR)
                         if (s >= 2) {
                             T f7[7];
-                            finish_p<T, FUSED>(rp, k, f7);
+                            finish_p<T, RP>(rp, k, f7);
                             park(zz, h, f7);
                         }
                 } else {
-                    RawV<T, FUSED> rv;
-                    load_rawv<T, FUSED>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
-                    finish_v<T, FUSED>(rv, u, v, w);
+                    RawV<T, RP> rv;
+                    load_rawv<T, RP>(rv, A.q, A.prim, n, poff(zz) + hcol[h]);
+                    finish_v<T, RP>(rv, u, v, w);
+                    if constexpr (HR)
+                        if (s >= 2) {
+                            RawP<T, RP> rp;
+                            load_rawp<T, RP>(rp, A.q, A.prim, n, poff(zz) + hcol[h]);
+                            T f7[7];
+                            finish_p<T, RP>(rp, k, f7);
+                            park(zz, h, f7);
+                        }
                 }
                 V[hidxV[h]] = u;
                 V[FOV + hidxV[h]] = v;
@@ -882,19 +923,19 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
 
     // prefetched halo values for the first iteration: fused form, raw q of
     // plane z0+2; stored-primitive form, velocity of plane z0+2 and the
-    // seven plane fields of plane z0
-    RawP<T, FUSED> hq[HPT];
-    RawV<T, FUSED> hv[FUSED ? 1 : HPT];
-    RawP<T, FUSED> hz[FUSED && !HR ? HPT : 1];  // fused, no ring: raw q of plane z
+    // seven plane fields of plane z0 (of plane z0+2 with the halo ring)
+    RawP<T, RP> hq[HPT];
+    RawV<T, RP> hv[RP ? 1 : HPT];
+    RawP<T, RP> hz[RP && !HR ? HPT : 1];  // fused, no ring: raw q of plane z
 #pragma unroll
     for (int h = 0; h < HPT; ++h)
         if (hval[h]) {
-            if constexpr (FUSED) {
-                load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
-                if constexpr (!HR) load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z0) + hcol[h]);
+            if constexpr (RP) {
+                load_rawp<T, RP>(hq[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+                if constexpr (!HR) load_rawp<T, RP>(hz[h], A.q, A.prim, n, poff(z0) + hcol[h]);
             } else {
-                load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
-                load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z0) + hcol[h]);
+                load_rawv<T, RP>(hv[h], A.q, A.prim, n, poff(z0 + 2) + hcol[h]);
+                load_rawp<T, RP>(hq[h], A.q, A.prim, n, poff(HR ? z0 + 2 : z0) + hcol[h]);
             }
         }
 
@@ -928,7 +969,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // at raised priority until it (double precision: -2.6% on the fused
         // 512^3 stage; single precision, which is bound by memory, gains
         // nothing)
-        constexpr bool kHaloPrio = FUSED && sizeof(T) == 8;
+        constexpr bool kHaloPrio = RP && sizeof(T) == 8;
         if constexpr (kHaloPrio) {
             if (tid < NHALO) __builtin_amdgcn_s_setprio(2);
         }
@@ -962,7 +1003,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             if (hval[h]) {
                 T u, v, w;
                 T f7[7];
-                if constexpr (FUSED) {
+                if constexpr (RP) {
                     // velocity of the leading plane from the raw values of z+2
                     const T ir = fast_rcp(hq[h].a[0]);
                     u = hq[h].a[1] * ir;
@@ -970,21 +1011,25 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
                     w = hq[h].a[3] * ir;
                     if constexpr (HR) {
                         // plane-z fields parked two planes ago; park those of z+2
-                        f7[0] = hring(z, 0, h);
-                        f7[4] = hring(z, 1, h);
-                        f7[5] = hring(z, 2, h);
-                        f7[6] = hring(z, 3, h);
+                        unpark(z, h, f7);
                         T g7[7];
-                        finish_p<T, FUSED>(hq[h], k, g7);
+                        finish_p<T, RP>(hq[h], k, g7);
                         park(z + 2, h, g7);
                     } else {
                         // plane-z fields from the raw values fetched in the
                         // previous iteration
-                        finish_p<T, FUSED>(hz[h], k, f7);
+                        finish_p<T, RP>(hz[h], k, f7);
                     }
                 } else {
-                    finish_v<T, FUSED>(hv[h], u, v, w);
-                    finish_p<T, FUSED>(hq[h], k, f7);
+                    finish_v<T, RP>(hv[h], u, v, w);
+                    if constexpr (HR) {
+                        unpark(z, h, f7);
+                        T g7[7];
+                        finish_p<T, RP>(hq[h], k, g7);
+                        park(z + 2, h, g7);
+                    } else {
+                        finish_p<T, RP>(hq[h], k, f7);
+                    }
                 }
                 Vl[hidxV[h]] = u;
                 Vl[FOV + hidxV[h]] = v;
@@ -1008,20 +1053,20 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // The unfused double-precision recompute forms fetch after the
         // compute instead: the prefetched stored primitives do not fit beside
         // their residual (52-84 B of spills per lane against 19-36).
-        constexpr bool kLatePrefetch = RC && !FUSED && sizeof(T) == 8;
-        Raw<T, FUSED> nxt;
+        constexpr bool kLatePrefetch = RC && !RP && sizeof(T) == 8;
+        Raw<T, RP> nxt;
         auto fetch_next = [&]() {
-            load_raw<T, FUSED>(nxt, A.q, A.prim, n, poff(z + 3) + col);
+            load_raw<T, RP>(nxt, A.q, A.prim, n, poff(z + 3) + col);
 #pragma unroll
             for (int h = 0; h < HPT; ++h)
                 if (hval[h]) {
-                    if constexpr (FUSED) {
-                        load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                    if constexpr (RP) {
+                        load_rawp<T, RP>(hq[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
                         if constexpr (!HR)
-                            load_rawp<T, FUSED>(hz[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                            load_rawp<T, RP>(hz[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
                     } else {
-                        load_rawv<T, FUSED>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
-                        load_rawp<T, FUSED>(hq[h], A.q, A.prim, n, poff(z + 1) + hcol[h]);
+                        load_rawv<T, RP>(hv[h], A.q, A.prim, n, poff(z + 3) + hcol[h]);
+                        load_rawp<T, RP>(hq[h], A.q, A.prim, n, poff(HR ? z + 3 : z + 1) + hcol[h]);
                     }
                 }
         };
@@ -1325,7 +1370,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             Xw[s] = Xw[s + 1];
             Yw[s] = Yw[s + 1];
         }
-        Qz[4] = finish<T, FUSED>(nxt, k, unew);
+        Qz[4] = finish<T, RP>(nxt, k, unew);
         if constexpr (SS && !RC) {
             Xs[4] = gnx[0];
             Xw[4] = gnx[1];
@@ -1410,7 +1455,7 @@ k_ra_zsweep(ZArgs<T> A) {
     using G = Geom<TX, TY>;
     __shared__ T sP[PlaneLds<SS>::kBuffers * PlaneLds<SS>::kFields * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, FUSED, SS, RC>() * 3 * G::NPL];
-    __shared__ T sH[halo_ring<T, TY, FUSED, MON>() ? 2 * kPF * G::NHALO : 1];
+    __shared__ T sH[halo_ring<T, TY, FUSED, MON, SS>() ? 2 * halo_fields<SS>() * G::NHALO : 1];
     __shared__ T sD[d_ring<T, TY, SS, RC>() ? 3 * G::DSZ : 1];
     __shared__ double2 sM[MON && sizeof(T) == 4 ? TX * TY : 1];
     zsweep_tile<T, TX, TY, FUSED, SS, MON, RC, GM>(A, xcd_tile(blockIdx.x, gridDim.x), sP, sV, sH,
@@ -1542,6 +1587,35 @@ void launch_ss_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     else launch_ss_set<T, kGradAll>(a, zchunk, tile_y, s, recompute);
 }
 
+template <typename T, int GM>
+void launch_ss_fused_set(const ZArgs<T>& a, int zchunk, int tile_y, hipStream_t s) {
+    if (tile_y == 16) launch_tiles<T, kTX, 16, true, true, false, false, GM>(a, zchunk, s);
+    else launch_tiles<T, kTX, 8, true, true, false, false, GM>(a, zchunk, s);
+}
+
+template <typename T>
+void launch_ss_fused(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
+                     T* qout, double* qacc, const StageCoef& sc, int zchunk, int tile_y,
+                     hipStream_t s, int gmask) {
+    TimerScope ts("ss_fused", s);
+    ZArgs<T> a{};
+    a.d = d;
+    a.k = c;
+    a.q = q;
+    a.prim = prim;
+    a.grad = grad;
+    a.qout = qout;
+    a.qacc = qacc;
+    a.qacc_in = qacc;
+    a.acc_store = 1;
+    a.a_dt = sc.a_dt;
+    a.b_dt = sc.b_dt;
+    a.last = sc.last;
+    if (gmask == kGradDiag) launch_ss_fused_set<T, kGradDiag>(a, zchunk, tile_y, s);
+    else if (gmask == kGradPlane) launch_ss_fused_set<T, kGradPlane>(a, zchunk, tile_y, s);
+    else launch_ss_fused_set<T, kGradAll>(a, zchunk, tile_y, s);
+}
+
 template <typename T>
 void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
                      int nblocks, int tile_y, hipStream_t s, bool recompute, int store_acc) {
@@ -1647,6 +1721,9 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
                                       int, int, hipStream_t, bool);                         \
     template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
                                       const T*, T*, int, int, hipStream_t, bool, int);      \
+    template void launch_ss_fused<T>(const Dims&, const Coef<T>&, const T*, const T*,       \
+                                     const T*, T*, double*, const StageCoef&, int, int,     \
+                                     hipStream_t, int);                                     \
     template void launch_ra_fused<T>(const Dims&, const Coef<T>&, const T*, T*, double*,    \
                                      const StageCoef&, int, int, hipStream_t, double*, bool);
 NSF_INST(float)

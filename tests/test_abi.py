@@ -66,6 +66,9 @@ def test_workspace_sizes(nsf):
     # the fused form adds one rotating state (the other shares the primitives)
     fused = nsf.workspace_bytes((n, n, n), "RA", "f64", {"fuse": 1})
     assert 5 * npts * 8 <= fused - sizes["RA"] < 6 * npts * 8
+    # so does the fused SS form (the other is the caller's r)
+    ss_fused = nsf.workspace_bytes((n, n, n), "SS", "f64", {"fuse": 1})
+    assert 5 * npts * 8 <= ss_fused - sizes["SS"] < 6 * npts * 8
 
 
 @pytest.mark.parametrize("shape", [(4, 8, 8), (8, 0, 8), (8, 8, -3), (2048, 2048, 1024),
@@ -236,7 +239,7 @@ def test_tune_cache_load_skips_invalid_lines(nsf, tmp_path):
              base % (7, 16, 32, 0, 0),   # no such algorithm
              base % (3, 12, 32, 1, 0),   # tile height 12
              base % (3, 16, 99, 1, 0),   # z-chunk beyond the grid
-             base % (2, 16, 32, 1, 0),   # SS cannot fuse
+             base % (4, 16, 32, 1, 0),   # RS has no fused form
              base % (2, 16, 32, 0, 4),   # in-plane store set on a 3D grid
              base % (2, 16, 32, 0, 3)]   # SS, diagonal store set: valid
     path = tmp_path / "cache.jsonl"

@@ -77,7 +77,7 @@ def test_2d_no_z_momentum_generated(variant, tune):
 
 
 @pytest.mark.parametrize("variant,tune", [("RA", {"fuse": 1}), ("RA", None), ("SS", None),
-                                          ("BL", None)])
+                                          ("SS", {"fuse": 1}), ("BL", None)])
 def test_2d_rk_ten_steps(variant, tune):
     shape = (48, 40, 1)
     print(f"case 2d rk10 {variant} {tune}", flush=True)

@@ -96,7 +96,7 @@ def test_512_monitored_fused_step_f32_form_sampled_planes():
 
 
 @pytest.mark.parametrize("variant,tune", [("BL", None), ("SS", None), ("RA", None), ("RS", None),
-                                          ("SN", None), ("RA", {"fuse": 1})])
+                                          ("SN", None), ("RA", {"fuse": 1}), ("SS", {"fuse": 1})])
 def test_256_monitored_step_sampled_planes(variant, tune):
     # the 256^3 comparison of the algorithms (pointwise +-1e-3, seed 1610,
     # dt = 8.4625e-4): each variant's monitored step at its default tuning

@@ -249,7 +249,7 @@ def test_rhs_f64_parity_ra_tunings(shape, tune, variant):
 
 
 @pytest.mark.parametrize("zchunk", [0, 5])
-@pytest.mark.parametrize("variant", ["RA", "SN"])
+@pytest.mark.parametrize("variant", ["RA", "SN", "SS"])
 def test_rk_fused_ten_steps_tgv32(zchunk, variant):
     shape, n = (32, 32, 32), 32
     dt = W.tgv_dt(n)
@@ -266,10 +266,11 @@ def test_rk_fused_ten_steps_tgv32(zchunk, variant):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(32, 32, 32), (40, 36, 50), (5, 6, 7), (70, 11, 9)])
 @pytest.mark.parametrize("block_y", [8, 16])
-@pytest.mark.parametrize("variant", ["RA", "SN"])
+@pytest.mark.parametrize("variant", ["RA", "SN", "SS"])
 def test_rk_fused_matches_unfused(precision, shape, block_y, variant):
-    # the fused stage kernel (primitives recomputed in the tile, update in
-    # the epilogue) agrees with the stored-primitive path to round-off: to
+    # the fused stage kernel (update in the epilogue; in RA and SN the
+    # primitives recomputed in the tile) agrees with the separate-update
+    # path to round-off: to
     # 1e-13 (FP64) or 1e-5 (FP32), or within 4x the stored-primitive path's
     # own error against the extended-precision oracle, per field. The two
     # builds may fuse multiply-adds differently, and rho w (small next to
@@ -288,6 +289,33 @@ def test_rk_fused_matches_unfused(precision, shape, block_y, variant):
         bar = np.maximum(tol, 4 * rel_err(out["plain"][i], ref))
         err = rel_err(out["fused"][i], out["plain"][i])
         assert np.all(err <= bar), (i, err, bar)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("tune", [{"gstore": 3}, {"gstore": 3, "block_y": 8, "zchunk": 7},
+                                  {"block_y": 16, "zchunk": 5}])
+def test_ss_fused_store_sets_match_unfused(precision, tune):
+    # the fused SS stage with the diagonal store set and explicit tiles:
+    # three RK steps agree with the separate-update SS path of the same
+    # tuning to round-off (the residual code is the same; the two builds
+    # may contract multiply-adds differently), and with the oracle
+    shape = (40, 36, 50)
+    print(f"case ss fused store set {precision} {tune}", flush=True)
+    tgv = W.tgv_pointwise(23, 1e-2)
+    out = {}
+    for name, fuse in (("plain", 0), ("fused", 1)):
+        s = nsf.Solver(shape, PHYS, "SS", precision, tune=dict(tune, fuse=fuse))
+        s.init(tgv)
+        s.step(2e-3, 3)
+        torch.cuda.synchronize()
+        out[name] = (s.q.cpu().numpy().astype(np.float64), s.q_acc.cpu().numpy())
+    ref = O.rk_step(O.init(shape, PHYS, tgv, prec="ld"), PHYS, 2e-3, 3, prec="ld")
+    tol = 1e-13 if precision == "f64" else 1e-5
+    for i in (0, 1):
+        bar = np.maximum(tol, 4 * rel_err(out["plain"][i], ref))
+        assert np.all(rel_err(out["fused"][i], out["plain"][i]) <= bar), i
+    if precision == "f64":
+        assert np.all(rel_err(out["fused"][1], ref) <= 1e-10)
 
 
 def test_rk_f32_form_against_f64_oracle():

@@ -41,16 +41,17 @@ def test_autotune_choice_is_parity_gated_and_used_by_auto(tmp_path, precision):
 
 
 FAMILIES = ("ra_zsweep", "sn_zsweep", "ss_zsweep", "rs_zsweep", "ra_fused", "ra_fused_first",
-            "ra_fused_last", "sn_fused", "sn_fused_first", "sn_fused_last")
+            "ra_fused_last", "sn_fused", "sn_fused_first", "sn_fused_last", "ss_fused")
 
 
 @pytest.mark.parametrize("variant,tune,family", [
     ("RA", None, "ra_zsweep"), ("SN", None, "sn_zsweep"), ("SS", None, "ss_zsweep"),
-    ("RS", None, "rs_zsweep"), ("RA", {"fuse": 1}, "ra_fused"), ("SN", {"fuse": 1}, "sn_fused")])
+    ("RS", None, "rs_zsweep"), ("RA", {"fuse": 1}, "ra_fused"), ("SN", {"fuse": 1}, "sn_fused"),
+    ("SS", {"fuse": 1}, "ss_fused")])
 def test_each_algorithm_runs_its_own_kernel(variant, tune, family):
     # RA, SN, RS and SS are separate kernels: two RK steps of each launch six
-    # kernels of its own family (the fused stages: first substep, middle,
-    # third without and with the q_acc store) and none of the others'
+    # kernels of its own family (the fused SN and RA stages: first substep,
+    # middle, third without and with the q_acc store) and none of the others'
     shape = (40, 36, 50)
     s = nsf.Solver(shape, PHYS, variant, "f64", tune=tune)
     s.init(W.tgv_pointwise(3, 1e-3))
@@ -64,7 +65,7 @@ def test_each_algorithm_runs_its_own_kernel(variant, tune, family):
     own = {f: c for f, c in counts.items() if f.startswith(family)}
     assert sum(own.values()) == 6, counts
     assert all(c == 0 for f, c in counts.items() if f not in own), counts
-    if tune:  # fused double precision: 2 first, 2 middle + 1 final third, 1 third
+    if tune and variant != "SS":  # fused double precision: 2 first, 2 middle + 1 final third, 1 third
         assert (own[family + "_first"], own[family], own[family + "_last"]) == (2, 3, 1), own
 
 
