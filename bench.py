@@ -55,7 +55,7 @@ FAMILY_BYTES = {
     "rs_zsweep": (192, 96),       # RS: q, prims, 9 gradients -> r
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
     "ss_naive": (192, 96),        # q, prims, 9 gradients -> r
-    "ss_grad": (96, 48),          # u, v, w -> 9 gradients
+    "ss_prims_grad": (152, 76),   # q -> u, v, w, p, T and 9 gradients (one pass)
     "ss_zsweep": (192, 96),       # q, prims, 9 gradients -> r
     "ss_fused": (272, 176),       # fused SS: q, prims, 9 gradients, q_acc -> q_next, q_acc
     "bl_deriv": (16, 8),          # one field -> one derivative
@@ -111,8 +111,8 @@ def families(variant, tune):
     if tune and tune.get("naive"):
         return ["prims", "ss_grad_naive", "ss_naive", "update", "diag"]
     if variant == "SS" and tune and tune.get("fuse"):
-        return ["prims", "ss_grad", "ss_fused", "diag"]
-    return ["prims", "ss_grad", "rs_zsweep" if variant == "RS" else "ss_zsweep", "update", "diag"]
+        return ["ss_prims_grad", "ss_fused", "diag"]
+    return ["ss_prims_grad", "rs_zsweep" if variant == "RS" else "ss_zsweep", "update", "diag"]
 
 
 def log(msg: str) -> None:

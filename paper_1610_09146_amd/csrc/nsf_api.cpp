@@ -319,13 +319,14 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
         case NSF_SS:
         case NSF_RS: {
             T* grad = (T*)(work + L.deriv);
-            launch_prims<T>(d, c, q, prim, s);
             if (tune && tune->naive) {
+                launch_prims<T>(d, c, q, prim, s);
                 launch_ss_grad_naive<T>(d, c, prim, grad, s);
                 launch_ss_naive<T>(d, c, q, prim, grad, r, s);
             } else {
+                // the primitive and gradient loops in one pass (same values)
                 const int gm = gmask_of(d, variant, tune);
-                launch_ss_grad<T>(d, c, prim, grad, gm, s);
+                launch_ss_prims_grad<T>(d, c, q, prim, grad, gm, s);
                 launch_ss_zsweep<T>(d, c, q, prim, grad, r, zchunk_of(d, tune),
                                     tile_y_of(d, tune, sizeof(T)), s, variant == NSF_RS, gm);
             }
@@ -401,8 +402,7 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.a_dt = st < 2 ? A[st] * dt : 0.0;
                 sc.b_dt = B[st] * dt;
                 sc.last = st == 2;
-                launch_prims<T>(d, c, in[st], prim, s);
-                launch_ss_grad<T>(d, c, prim, grad, gm, s);
+                launch_ss_prims_grad<T>(d, c, in[st], prim, grad, gm, s);
                 launch_ss_fused<T>(d, c, in[st], prim, grad, out[st], qacc, sc, zc, ty, s, gm);
             }
         }
@@ -631,7 +631,8 @@ int nsf_device_copy(const void* src, void* dst, size_t bytes, void* stream) {
 static const char* kTimerNames =
     "init,prims,update,bl_product,bl_deriv,bl_assemble,ra_naive,ra_zsweep,ra_fused,ra_fused_mon,"
     "ra_fused_first,ra_fused_last,sn_zsweep,sn_fused,sn_fused_mon,sn_fused_first,sn_fused_last,"
-    "ss_grad_naive,ss_naive,ss_grad,ss_zsweep,ss_fused,rs_zsweep,diag,copy,ra_batch,batch_step";
+    "ss_grad_naive,ss_naive,ss_prims_grad,ss_zsweep,ss_fused,rs_zsweep,diag,copy,ra_batch,"
+    "batch_step";
 
 const char* nsf_timer_names(void) { return kTimerNames; }
 

@@ -1,11 +1,12 @@
-// SS / RS gradient loop (paper Section 2, RS and SS paragraphs): the first
-// derivatives of the velocity, G_ab = D_b u_a, of a store set (bit 3a + b
-// of the mask GM) stored in work arrays, the stored ones in order of 3a + b:
-// all nine (the paper's 3D set), the three diagonal ones, or the four
-// in-plane ones of a two-dimensional grid (the paper's 2D count).
-// z-marching tiles: the stored velocity of each plane (with a two-point x-y
-// halo) enters a five-plane LDS ring once; x, y and z differences of the
-// centre plane are taken from the ring.
+// SS / RS primitive and gradient loops (paper Section 2, RS and SS
+// paragraphs) in one pass: the primitives u, v, w, p, T (eqs (9)-(10)) and
+// the first derivatives of the velocity, G_ab = D_b u_a, of a store set
+// (bit 3a + b of the mask GM) stored in work arrays, the stored ones in
+// order of 3a + b: all nine (the paper's 3D set), the three diagonal ones,
+// or the four in-plane ones of a two-dimensional grid (the paper's 2D
+// count). z-marching tiles: the velocity of each plane (with a two-point x-y
+// halo), formed from q, enters a five-plane LDS ring once; x, y and z
+// differences of the centre plane are taken from the ring.
 #include "nsf_internal.h"
 
 namespace nsf {
@@ -52,14 +53,21 @@ struct GradArgs {
     int zchunk, tiles_x, tiles_y;
 };
 
+// Primitives and gradients in one pass: the same tile reads q instead of
+// the stored velocity, forms u, v, w, p, T of its own points (the
+// primitive loop's arithmetic, so the stored values are the same bits) and
+// the velocity of its halo points, and writes the primitives of the chunk's
+// planes beside the store set's gradients. 152 bytes per point (double)
+// instead of the 80 + 96 of the two loops.
 template <typename T, int GM>
-__global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restrict__ prim,
-                                                 T* __restrict__ grad) {
-    // array of gradient (a, b): the number of stored gradients before it
+__global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* __restrict__ q,
+                                                       T* __restrict__ prim,
+                                                       T* __restrict__ grad) {
     auto slot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
     auto stored = [](int a, int b) { return (GM >> (3 * a + b)) & 1; };
     __shared__ T sV[kRing * 3 * kNPL];
     const Dims d = A.d;
+    const Coef<T> c = A.c;
     const size_t n = d.npts;
     const size_t plane = (size_t)d.nx * d.ny;
     const int t = xcd_tile_g(blockIdx.x, gridDim.x);
@@ -82,34 +90,51 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
         hidx = hy * kLX + hx;
         hcol = (size_t)pmodg(y0 + hy - 2, d.ny) * d.nx + pmodg(x0 + hx - 2, d.nx);
     }
-    // the velocity of plane zz at this thread's point and halo point,
-    // fetched one plane ahead of use so the load latency overlaps a plane's
-    // work
+    // raw conserved values of plane zz at this thread's point (five) and
+    // halo point (density and momenta), fetched one plane ahead of use. The
+    // density and momenta of a point are also the neighbouring tiles' halo,
+    // so they stay in the L2 (read past it, they came from HBM twice: 2.2x
+    // the algorithmic reads at 512^3); the energy, read once, streams past.
     struct Raw {
-        T own[3], halo[3];
+        T own[5], halo[4];
     };
     auto fetch = [&](int zz) {
         Raw r;
         const size_t po = (size_t)pmodg(zz, d.nz) * plane;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) r.own[a] = prim[a * n + po + col];
+        for (int f = 0; f < 4; ++f) r.own[f] = q[f * n + po + col];
+        r.own[4] = ld_nt(q + 4 * n + po + col);
         if (hval)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) r.halo[a] = prim[a * n + po + hcol];
+            for (int f = 0; f < 4; ++f) r.halo[f] = q[f * n + po + hcol];
         return r;
     };
+    // velocity into the ring; the primitives of the chunk's own planes out
     auto enter = [&](int zz, const Raw& r) {
         T* V = sV + pmodg(zz, kRing) * 3 * kNPL;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) V[a * kNPL + own] = r.own[a];
-        if (hval)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) V[a * kNPL + hidx] = r.halo[a];
+        const Prim<T> P = primitives(r.own[0], r.own[1], r.own[2], r.own[3], r.own[4], c);
+        V[own] = P.u;
+        V[kNPL + own] = P.v;
+        V[2 * kNPL + own] = P.w;
+        if (hval) {
+            const T ir = fast_rcp(r.halo[0]);
+            V[hidx] = r.halo[1] * ir;
+            V[kNPL + hidx] = r.halo[2] * ir;
+            V[2 * kNPL + hidx] = r.halo[3] * ir;
+        }
+        if (active && zz >= z0 && zz < z1) {
+            const size_t o = (size_t)zz * plane + col;
+            st_nt(P.u, prim + o);
+            st_nt(P.v, prim + n + o);
+            st_nt(P.w, prim + 2 * n + o);
+            st_nt(P.p, prim + 3 * n + o);
+            st_nt(P.t, prim + 4 * n + o);
+        }
     };
     for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s));
     Raw nxt = fetch(z0 + 2);
-    const T a1x = A.c.a1[0], a2x = A.c.a2[0], a1y = A.c.a1[1], a2y = A.c.a2[1];
-    const T a1z = A.c.a1[2], a2z = A.c.a2[2];
+    const T a1x = c.a1[0], a2x = c.a2[0], a1y = c.a1[1], a2y = c.a2[1];
+    const T a1z = c.a1[2], a2z = c.a2[2];
     for (int z = z0; z < z1; ++z) {
         const Raw cur = nxt;
         if (z + 1 < z1) nxt = fetch(z + 3);
@@ -125,7 +150,6 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const T* F = Vc + a * kNPL;
-                // streamed: the residual sweep reads them back from HBM (7% faster)
                 if (stored(a, 0))
                     st_nt(a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]),
                           grad + slot(a, 0) * n + o);
@@ -145,9 +169,9 @@ __global__ void __launch_bounds__(kNT) k_ss_grad(GradArgs<T> A, const T* __restr
 }  // namespace
 
 template <typename T>
-void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int gmask,
-                    hipStream_t s) {
-    TimerScope ts("ss_grad", s);
+void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
+                          int gmask, hipStream_t s) {
+    TimerScope ts("ss_prims_grad", s);
     GradArgs<T> a;
     a.d = d;
     a.c = c;
@@ -157,16 +181,16 @@ void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int
     const int tz = (d.nz + a.zchunk - 1) / a.zchunk;
     const dim3 grid(a.tiles_x * a.tiles_y * tz);
     if (gmask == kGradDiag)
-        hipLaunchKernelGGL((k_ss_grad<T, kGradDiag>), grid, dim3(kNT), 0, s, a, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradDiag>), grid, dim3(kNT), 0, s, a, q, prim, grad);
     else if (gmask == kGradPlane)
-        hipLaunchKernelGGL((k_ss_grad<T, kGradPlane>), grid, dim3(kNT), 0, s, a, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradPlane>), grid, dim3(kNT), 0, s, a, q, prim, grad);
     else
-        hipLaunchKernelGGL((k_ss_grad<T, kGradAll>), grid, dim3(kNT), 0, s, a, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradAll>), grid, dim3(kNT), 0, s, a, q, prim, grad);
 }
 
-template void launch_ss_grad<float>(const Dims&, const Coef<float>&, const float*, float*, int,
-                                    hipStream_t);
-template void launch_ss_grad<double>(const Dims&, const Coef<double>&, const double*, double*, int,
-                                     hipStream_t);
+template void launch_ss_prims_grad<float>(const Dims&, const Coef<float>&, const float*, float*,
+                                          float*, int, hipStream_t);
+template void launch_ss_prims_grad<double>(const Dims&, const Coef<double>&, const double*,
+                                           double*, double*, int, hipStream_t);
 
 }  // namespace nsf

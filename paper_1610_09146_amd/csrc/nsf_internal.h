@@ -161,10 +161,11 @@ template <typename T>
 void launch_ss_fused(const Dims& d, const Coef<T>& c, const T* q, const T* prim, const T* grad,
                      T* qout, double* qacc, const StageCoef& sc, int zchunk, int tile_y,
                      hipStream_t s, int gmask);
-// SS gradient loop: the store set's G_ab = D_b u_a into arrays (z-marching tiles).
+// SS / RS primitive and gradient loops in one pass (z-marching tiles): prim =
+// u, v, w, p, T of q (eqs (9)-(10)) and the store set's G_ab = D_b u_a.
 template <typename T>
-void launch_ss_grad(const Dims& d, const Coef<T>& c, const T* prim, T* grad, int gmask,
-                    hipStream_t s);
+void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
+                          int gmask, hipStream_t s);
 // Fused stage with no derivative arrays (RA with recompute = true, SN
 // otherwise): primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),
