@@ -432,7 +432,7 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--variant", default="AUTO",
                     help="AUTO = the autotuner's pick for this grid (default), or BL/RA/SS/SN/RS")
-    ap.add_argument("--fuse", type=int, default=1, help="RA/SN: fused stage kernel (1) or not (0)")
+    ap.add_argument("--fuse", type=int, default=1, help="RA/SN/SS: fused stage kernel (1) or not (0)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"],
                     help="precision of the main line (the metric is quoted for f64)")
     ap.add_argument("--block-y", type=int, default=0, help="tile height 8/16 (explicit variant)")
