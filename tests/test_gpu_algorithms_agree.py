@@ -3,7 +3,7 @@
 The paper validates BL against reference data and then checks that each
 other algorithm gives BL's results up to machine precision. Here the five
 algorithms (BL, RA, SN, SS, RS), the fused forms of SN, RA and SS and the
-three-gradient store set of SS advance the same Taylor-Green vortex for 150
+three-gradient store set of SS and RS advance the same Taylor-Green vortex for 150
 monitored steps at 64^3 (t = 0.51, before the flow turns turbulent), in
 double precision; their final states and their kinetic-energy and enstrophy
 histories are compared with BL's.
