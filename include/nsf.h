@@ -25,9 +25,10 @@
  *   - Precision: NSF_F64 -> q, r are double; NSF_F32 -> q, r are float
  *     (fields and stencil arithmetic in single precision). The Runge-Kutta
  *     accumulator q_acc and all reductions are always double.
- *   - Memory: every pointer argument named q, q_acc, r, work is device
- *     memory owned by the caller; the library only borrows it for the call
- *     and allocates no device memory outside nsf_batch_create.
+ *   - Memory: every pointer argument named q, q_acc, r, work, workspace
+ *     is device memory owned by the caller; the library only borrows it for
+ *     the call and allocates no device memory outside the nsf_batch_create
+ *     family (its descriptor tables, freed by nsf_batch_destroy).
  *   - Streams: `stream` is a hipStream_t passed as void* (NULL = default
  *     stream). Calls enqueue work and return without waiting, except where
  *     stated (diagnostics, autotune, batch diagnostics).
@@ -254,8 +255,10 @@ int nsf_diagnostics_noalloc(const nsf_grid *g, const nsf_phys *phys, int precisi
  * fastest count as ties, resolved toward the default tuning and then the
  * larger z-chunk. The winner is recorded for NSF_AUTO and, if cache_path
  * is not NULL, appended as one JSON line to that file. Synchronous.
- * Allocates its own device buffers (five to seven states and the largest
- * candidate's work) for the duration of the call. */
+ * workspace: caller-owned device memory of at least
+ * nsf_autotune_workspace_bytes bytes (seven to nine states and the largest
+ * candidate's work), used for the duration of the call; NSF_EWORKSPACE if
+ * smaller. The library allocates no device memory here. */
 #define NSF_TUNE_QUICK 1 /* skip BL and the untiled kernels */
 typedef struct {
     int32_t variant;
@@ -264,8 +267,12 @@ typedef struct {
     double parity_rel_err; /* worst per-field relative residual difference */
 } nsf_tune_result;
 
+/* Bytes of the workspace nsf_autotune needs for this grid, precision and
+ * flags, written to *bytes. */
+int nsf_autotune_workspace_bytes(const nsf_grid *g, int precision, int flags, size_t *bytes);
 int nsf_autotune(const nsf_grid *g, const nsf_phys *phys, int precision, int flags, int32_t steps,
-                 const char *cache_path, nsf_tune_result *best, void *stream);
+                 const char *cache_path, void *workspace, size_t workspace_bytes,
+                 nsf_tune_result *best, void *stream);
 /* Load gfx950 entries of a cache file written by nsf_autotune (later lines
  * override earlier ones). A line that names no configuration the library
  * runs on its grid (algorithm, tile height, z-chunk, flags, store set) is
@@ -326,11 +333,17 @@ int nsf_batch_create_variant(int32_t count, const nsf_grid *grids, const nsf_phy
  * toward SN, 16 rows and the default chunks. Writes the winner to
  * *best_variant and *best_tune (for nsf_batch_create_variant) and its rate
  * in grid-point RHS evaluations per second to *best_pt_rhs_per_s (may be
- * NULL). Synchronous; allocates five ensemble states and a batch work
- * buffer for the duration of the call. */
+ * NULL). Synchronous. workspace: caller-owned device memory of at least
+ * nsf_batch_autotune_workspace_bytes bytes (five ensemble states and a batch
+ * work area); NSF_EWORKSPACE if smaller. Device memory is allocated only by
+ * the nsf_batch_create_variant calls it makes (their descriptor tables,
+ * freed before it returns). */
+int nsf_batch_autotune_workspace_bytes(int32_t count, const nsf_grid *grids, int precision,
+                                       size_t *bytes);
 int nsf_batch_autotune(int32_t count, const nsf_grid *grids, const nsf_phys *phys,
-                       const double *dt, int precision, int32_t steps, int32_t *best_variant,
-                       nsf_tuning *best_tune, double *best_pt_rhs_per_s, void *stream);
+                       const double *dt, int precision, int32_t steps, void *workspace,
+                       size_t workspace_bytes, int32_t *best_variant, nsf_tuning *best_tune,
+                       double *best_pt_rhs_per_s, void *stream);
 
 /* Advance every instance nsteps steps by replaying the captured graph on
  * `stream`; on completion q and q_acc hold the new states (in double

@@ -276,12 +276,19 @@ bool tune_lookup(const Dims& d, int precision, int* variant, nsf_tuning* tune) {
 }
 }  // namespace nsf
 
-extern "C" {
+namespace {
 
-int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int flags, int32_t steps,
-                 const char* cache_path, nsf_tune_result* best, void* stream) {
-    if (!g || !phys || !best) return tfail(NSF_EINVAL, "autotune: NULL argument");
-    if (precision != NSF_F64 && precision != NSF_F32) return tfail(NSF_EINVAL, "autotune: precision");
+// Device buffers of one nsf_autotune call, carved from the caller's work
+// area (256-byte aligned): initial state and accumulator, working copies,
+// candidate residual, reference residual and step (double), reduction
+// partials, the largest candidate's work; single precision also the double
+// state and its residual.
+struct TuneLayout {
+    size_t q0 = 0, q = 0, r = 0, qacc0 = 0, qacc = 0, rref = 0, qstep = 0, partial = 0,
+           q64 = 0, r64 = 0, work = 0, wmax = 0, total = 0;
+};
+
+int tune_layout(const nsf_grid* g, int precision, int flags, TuneLayout* L) {
     nsf_tuning ref;
     std::memset(&ref, 0, sizeof ref);
     ref.naive = 1;
@@ -289,6 +296,64 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     // the reference residual runs the untiled double-precision kernels
     int rc = nsf_workspace_bytes(g, NSF_RA, NSF_F64, &ref, &wmax);
     if (rc) return rc;
+    for (auto& c : candidates(g, flags)) {
+        size_t w = 0;
+        if ((rc = nsf_workspace_bytes(g, c.variant, precision, &c.tune, &w))) return rc;
+        wmax = std::max(wmax, w);
+    }
+    const size_t npts = (size_t)g->nx * g->ny * g->nz;
+    const size_t fb = 5 * npts * (precision == NSF_F32 ? 4 : 8), db = 5 * npts * sizeof(double);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L->q0 = take(fb);
+    L->q = take(fb);
+    L->r = take(fb);
+    L->qacc0 = take(db);
+    L->qacc = take(db);
+    L->rref = take(db);
+    L->qstep = take(db);
+    L->partial = take(3 * kDiffBlocks * sizeof(double));
+    if (precision == NSF_F32) {
+        L->q64 = take(db);
+        L->r64 = take(db);
+    }
+    L->work = take(wmax);
+    L->wmax = wmax;
+    L->total = off;
+    return NSF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nsf_autotune_workspace_bytes(const nsf_grid* g, int precision, int flags, size_t* bytes) {
+    if (!g || !bytes) return tfail(NSF_EINVAL, "autotune_workspace_bytes: NULL argument");
+    if (precision != NSF_F64 && precision != NSF_F32) return tfail(NSF_EINVAL, "autotune: precision");
+    TuneLayout L;
+    int rc = tune_layout(g, precision, flags, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return NSF_OK;
+}
+
+int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int flags, int32_t steps,
+                 const char* cache_path, void* workspace, size_t workspace_bytes,
+                 nsf_tune_result* best, void* stream) {
+    if (!g || !phys || !best || !workspace) return tfail(NSF_EINVAL, "autotune: NULL argument");
+    if (precision != NSF_F64 && precision != NSF_F32) return tfail(NSF_EINVAL, "autotune: precision");
+    nsf_tuning ref;
+    std::memset(&ref, 0, sizeof ref);
+    ref.naive = 1;
+    TuneLayout L;
+    int rc = tune_layout(g, precision, flags, &L);
+    if (rc) return rc;
+    if (workspace_bytes < L.total)
+        return set_error(NSF_EWORKSPACE, "autotune: workspace too small");
     if (steps < 1) steps = 2;
     hipStream_t s = (hipStream_t)stream;
     const Dims d{g->nx, g->ny, g->nz, (size_t)g->nx * g->ny * g->nz};
@@ -296,35 +361,23 @@ int nsf_autotune(const nsf_grid* g, const nsf_phys* phys, int precision, int fla
     const size_t es = f32 ? 4 : 8;
     const size_t fb = 5 * d.npts * es, db = 5 * d.npts * sizeof(double);
     std::vector<nsf_tune_result> cands = candidates(g, flags);
-    for (auto& c : cands) {
-        size_t w = 0;
-        if ((rc = nsf_workspace_bytes(g, c.variant, precision, &c.tune, &w))) return rc;
-        wmax = std::max(wmax, w);
-    }
-    // buffers: initial state and accumulator, working copies, candidate
-    // residual, reference residual (double); single precision also the
-    // double state and its residual
-    void *q0 = nullptr, *q = nullptr, *r = nullptr, *work = nullptr;
-    double *qacc0 = nullptr, *qacc = nullptr, *rref = nullptr, *partial = nullptr;
-    double *q64 = nullptr, *r64 = nullptr, *qstep = nullptr;
-    hipError_t e = hipMalloc(&q0, fb);
-    if (e == hipSuccess) e = hipMalloc(&q, fb);
-    if (e == hipSuccess) e = hipMalloc(&r, fb);
-    if (e == hipSuccess) e = hipMalloc((void**)&qacc0, db);
-    if (e == hipSuccess) e = hipMalloc((void**)&qacc, db);
-    if (e == hipSuccess) e = hipMalloc((void**)&rref, db);
-    if (e == hipSuccess) e = hipMalloc(&work, wmax);
-    if (e == hipSuccess) e = hipMalloc((void**)&partial, 3 * kDiffBlocks * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&qstep, db);
-    if (e == hipSuccess && f32) e = hipMalloc((void**)&q64, db);
-    if (e == hipSuccess && f32) e = hipMalloc((void**)&r64, db);
+    const size_t wmax = L.wmax;
+    char* base = (char*)workspace;
+    void* q0 = base + L.q0;
+    void* q = base + L.q;
+    void* r = base + L.r;
+    void* work = base + L.work;
+    double* qacc0 = (double*)(base + L.qacc0);
+    double* qacc = (double*)(base + L.qacc);
+    double* rref = (double*)(base + L.rref);
+    double* qstep = (double*)(base + L.qstep);
+    double* partial = (double*)(base + L.partial);
+    double* q64 = f32 ? (double*)(base + L.q64) : nullptr;
+    double* r64 = f32 ? (double*)(base + L.r64) : nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (e == hipSuccess) e = hipEventCreate(&t0);
+    hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     auto cleanup = [&]() {
-        for (void* p : {q0, q, r, work, (void*)qacc0, (void*)qacc, (void*)rref, (void*)partial,
-                        (void*)q64, (void*)r64, (void*)qstep})
-            if (p) (void)hipFree(p);
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
     };
@@ -505,52 +558,96 @@ int nsf_tune_get(const nsf_grid* g, int precision, nsf_tune_result* out) {
 // replays of the whole ensemble on the library's own copies of seeded
 // states. In a batch the work of many instances fills the GPU, so the
 // single-grid records (chosen for one grid alone) do not carry over.
+namespace {
+
+// Device buffers of one nsf_batch_autotune call, carved from the caller's
+// work area: per instance the state, accumulator, their initial copies and
+// the reference result (each 256-byte aligned), the batch work area and
+// reduction partials.
+struct BatchTuneLayout {
+    std::vector<size_t> off, aoff;  // per-instance offsets within a state / accumulator block
+    size_t q = 0, q0 = 0, qref = 0, qa = 0, qa0 = 0, work = 0, partial = 0, wbytes = 0,
+           total = 0, pts = 0;
+};
+
+int batch_tune_layout(int32_t count, const nsf_grid* grids, int precision, BatchTuneLayout* L) {
+    const size_t es = precision == NSF_F32 ? 4 : 8;
+    int rc = nsf_batch_workspace_bytes(count, grids, precision, &L->wbytes);
+    if (rc) return rc;
+    L->off.assign(count + 1, 0);
+    L->aoff.assign(count + 1, 0);
+    L->pts = 0;
+    for (int i = 0; i < count; ++i) {
+        const size_t n = (size_t)grids[i].nx * grids[i].ny * grids[i].nz;
+        L->pts += n;
+        L->off[i + 1] = L->off[i] + (5 * n * es + 255) / 256 * 256;
+        L->aoff[i + 1] = L->aoff[i] + (5 * n * sizeof(double) + 255) / 256 * 256;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += (bytes + 255) / 256 * 256;
+        return at;
+    };
+    L->q = take(L->off[count]);
+    L->q0 = take(L->off[count]);
+    L->qref = take(L->off[count]);
+    L->qa = take(L->aoff[count]);
+    L->qa0 = take(L->aoff[count]);
+    L->work = take(L->wbytes);
+    L->partial = take(2 * kDiffBlocks * sizeof(double));
+    L->total = off;
+    return NSF_OK;
+}
+
+}  // namespace
+
+extern "C" int nsf_batch_autotune_workspace_bytes(int32_t count, const nsf_grid* grids,
+                                                  int precision, size_t* bytes) {
+    if (!grids || !bytes || count < 1)
+        return tfail(NSF_EINVAL, "batch_autotune_workspace_bytes: NULL argument or count < 1");
+    if (precision != NSF_F64 && precision != NSF_F32)
+        return tfail(NSF_EINVAL, "batch_autotune: precision");
+    BatchTuneLayout L;
+    int rc = batch_tune_layout(count, grids, precision, &L);
+    if (rc) return rc;
+    *bytes = L.total;
+    return NSF_OK;
+}
+
 extern "C" int nsf_batch_autotune(int32_t count, const nsf_grid* grids, const nsf_phys* phys,
-                                  const double* dt, int precision, int32_t steps,
-                                  int32_t* best_variant, nsf_tuning* best_tune,
-                                  double* best_pt_rhs_per_s, void* stream) {
-    if (!grids || !phys || !dt || !best_variant || !best_tune || count < 1)
+                                  const double* dt, int precision, int32_t steps, void* workspace,
+                                  size_t workspace_bytes, int32_t* best_variant,
+                                  nsf_tuning* best_tune, double* best_pt_rhs_per_s, void* stream) {
+    if (!grids || !phys || !dt || !best_variant || !best_tune || !workspace || count < 1)
         return tfail(NSF_EINVAL, "batch_autotune: NULL argument or count < 1");
     if (precision != NSF_F64 && precision != NSF_F32)
         return tfail(NSF_EINVAL, "batch_autotune: precision");
     if (steps < 1) steps = 2;
     hipStream_t s = (hipStream_t)stream;
     const bool f32 = precision == NSF_F32;
-    const size_t es = f32 ? 4 : 8;
-    size_t wbytes = 0;
-    int rc = nsf_batch_workspace_bytes(count, grids, precision, &wbytes);
+    BatchTuneLayout L;
+    int rc = batch_tune_layout(count, grids, precision, &L);
     if (rc) return rc;
-    // per instance: state, accumulator, their initial copies, the reference result
-    std::vector<size_t> off(count + 1, 0);
-    size_t pts = 0;
-    for (int i = 0; i < count; ++i) {
-        const size_t n = (size_t)grids[i].nx * grids[i].ny * grids[i].nz;
-        pts += n;
-        off[i + 1] = off[i] + (5 * n * es + 255) / 256 * 256;
-    }
-    std::vector<size_t> aoff(count + 1, 0);
-    for (int i = 0; i < count; ++i) {
-        const size_t n = (size_t)grids[i].nx * grids[i].ny * grids[i].nz;
-        aoff[i + 1] = aoff[i] + 5 * n * sizeof(double);
-    }
-    char *q = nullptr, *q0 = nullptr, *qref = nullptr, *work = nullptr;
-    double *qa = nullptr, *qa0 = nullptr, *partial = nullptr;
-    hipError_t e = hipMalloc((void**)&q, off[count]);
-    if (e == hipSuccess) e = hipMalloc((void**)&q0, off[count]);
-    if (e == hipSuccess) e = hipMalloc((void**)&qref, off[count]);
-    if (e == hipSuccess) e = hipMalloc((void**)&qa, aoff[count]);
-    if (e == hipSuccess) e = hipMalloc((void**)&qa0, aoff[count]);
-    if (e == hipSuccess) e = hipMalloc((void**)&work, wbytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&partial, 2 * kDiffBlocks * sizeof(double));
+    if (workspace_bytes < L.total)
+        return set_error(NSF_EWORKSPACE, "batch_autotune: workspace too small");
+    const std::vector<size_t>& off = L.off;
+    const std::vector<size_t>& aoff = L.aoff;
+    const size_t pts = L.pts, wbytes = L.wbytes;
+    char* base = (char*)workspace;
+    char* q = base + L.q;
+    char* q0 = base + L.q0;
+    char* qref = base + L.qref;
+    char* work = base + L.work;
+    double* qa = (double*)(base + L.qa);
+    double* qa0 = (double*)(base + L.qa0);
+    double* partial = (double*)(base + L.partial);
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (e == hipSuccess) e = hipEventCreate(&t0);
+    hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     nsf_batch* b = nullptr;
     auto cleanup = [&]() {
         if (b) nsf_batch_destroy(b);
-        for (void* p : {(void*)q, (void*)q0, (void*)qref, (void*)qa, (void*)qa0, (void*)work,
-                        (void*)partial})
-            if (p) (void)hipFree(p);
         if (t0) (void)hipEventDestroy(t0);
         if (t1) (void)hipEventDestroy(t1);
     };

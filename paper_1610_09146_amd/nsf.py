@@ -110,14 +110,18 @@ def lib() -> ctypes.CDLL:
         L.nsf_batch_create_variant.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int,
                                                ctypes.c_int, Tu, ctypes.POINTER(vp),
                                                ctypes.POINTER(vp), vp, sz, vp, ctypes.POINTER(vp)]
-        L.nsf_batch_autotune.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, i32,
+        L.nsf_batch_autotune_workspace_bytes.argtypes = [i32, G, ctypes.c_int, ctypes.POINTER(sz)]
+        L.nsf_batch_autotune.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, i32, vp, sz,
                                          ctypes.POINTER(i32), Tu, ctypes.POINTER(d), vp]
         L.nsf_batch_destroy.argtypes = [vp]
         L.nsf_batch_create_tuned.argtypes = [i32, G, P, ctypes.POINTER(d), ctypes.c_int, Tu,
                                              ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp,
                                              ctypes.POINTER(vp)]
         TR = ctypes.POINTER(TuneResult)
-        L.nsf_autotune.argtypes = [G, P, ctypes.c_int, ctypes.c_int, i32, ctypes.c_char_p, TR, vp]
+        L.nsf_autotune_workspace_bytes.argtypes = [G, ctypes.c_int, ctypes.c_int,
+                                                   ctypes.POINTER(sz)]
+        L.nsf_autotune.argtypes = [G, P, ctypes.c_int, ctypes.c_int, i32, ctypes.c_char_p, vp, sz,
+                                   TR, vp]
         L.nsf_tune_load.argtypes = [ctypes.c_char_p]
         L.nsf_tune_get.argtypes = [G, ctypes.c_int, TR]
         _lib = L
@@ -284,9 +288,15 @@ def batch_autotune(instances, precision, steps: int = 3, stream=None) -> dict:
     phys = (Phys * n)(*[_phys(i["phys"]) for i in instances])
     dts = (ctypes.c_double * n)(*[float(i["dt"]) for i in instances])
     v, t, rate = ctypes.c_int32(0), Tuning(), ctypes.c_double(0)
+    nb = ctypes.c_size_t(0)
+    _check(lib().nsf_batch_autotune_workspace_bytes(n, grids, _precision(precision),
+                                                    ctypes.byref(nb)),
+           "nsf_batch_autotune_workspace_bytes")
+    work = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device="cuda")
     _check(lib().nsf_batch_autotune(n, grids, phys, dts, _precision(precision), int(steps),
-                                    ctypes.byref(v), ctypes.byref(t), ctypes.byref(rate),
-                                    _stream(stream)), "nsf_batch_autotune")
+                                    _ptr(work), int(nb.value), ctypes.byref(v), ctypes.byref(t),
+                                    ctypes.byref(rate), _stream(stream)), "nsf_batch_autotune")
+    del work
     return {"variant": VARIANT_NAMES.get(int(v.value)),
             "tune": {"block_y": t.block_y, "zchunk": t.zchunk}, "pt_rhs_per_s": float(rate.value)}
 
@@ -304,10 +314,17 @@ def autotune(shape, phys, precision, quick: bool = True, steps: int = 2,
     """Run the autotuner for one grid and precision (synchronous); the choice
     is recorded for variant "AUTO" in this process."""
     r = TuneResult()
+    flags = TUNE_QUICK if quick else 0
+    nb = ctypes.c_size_t(0)
+    _check(lib().nsf_autotune_workspace_bytes(ctypes.byref(_grid(shape)), _precision(precision),
+                                              flags, ctypes.byref(nb)),
+           "nsf_autotune_workspace_bytes")
+    work = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device="cuda")
     _check(lib().nsf_autotune(ctypes.byref(_grid(shape)), ctypes.byref(_phys(phys)),
-                              _precision(precision), TUNE_QUICK if quick else 0, int(steps),
-                              cache_path.encode() if cache_path else None, ctypes.byref(r),
-                              _stream(stream)), "nsf_autotune")
+                              _precision(precision), flags, int(steps),
+                              cache_path.encode() if cache_path else None, _ptr(work),
+                              int(nb.value), ctypes.byref(r), _stream(stream)), "nsf_autotune")
+    del work
     return _tune_dict(r)
 
 

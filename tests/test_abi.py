@@ -247,3 +247,50 @@ def test_tune_cache_load_skips_invalid_lines(nsf, tmp_path):
     assert nsf.tune_load(str(path)) == 2
     got = nsf.tune_get((48, 40, 36), "f64")
     assert got["variant"] == "SS" and got["tune"]["gstore"] == 3
+
+
+def test_autotune_workspace_queries(nsf):
+    """The autotuners take their device buffers from the caller: the size
+    queries cover seven states (nine in single precision) and the largest
+    candidate's work, or five ensemble states and the batch work area."""
+    L = nsf.lib()
+    n = 24
+    npts = n ** 3
+    g = nsf._grid((n, n, n))
+    got = {}
+    for prec in ("f64", "f32"):
+        b = ctypes.c_size_t(0)
+        assert L.nsf_autotune_workspace_bytes(ctypes.byref(g), nsf._precision(prec), 0,
+                                              ctypes.byref(b)) == 0
+        got[prec] = b.value
+    bl = nsf.workspace_bytes((n, n, n), "BL", "f64")
+    assert got["f64"] >= 3 * 5 * npts * 8 + 4 * 5 * npts * 8 + bl
+    assert got["f32"] >= 3 * 5 * npts * 4 + 6 * 5 * npts * 8
+    quick = ctypes.c_size_t(0)
+    assert L.nsf_autotune_workspace_bytes(ctypes.byref(g), 0, nsf.TUNE_QUICK,
+                                          ctypes.byref(quick)) == 0
+    assert quick.value < got["f64"]  # no BL candidate: a smaller work area
+    assert L.nsf_autotune_workspace_bytes(None, 0, 0, ctypes.byref(quick)) == nsf.EINVAL
+    assert L.nsf_autotune_workspace_bytes(ctypes.byref(g), 7, 0, ctypes.byref(quick)) == nsf.EINVAL
+    insts = [(16, 16, 16), (24, 24, 24)]
+    grids = (nsf.Grid * 2)(*[nsf._grid(s) for s in insts])
+    bb, wb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.nsf_batch_autotune_workspace_bytes(2, grids, 0, ctypes.byref(bb)) == 0
+    assert L.nsf_batch_workspace_bytes(2, grids, 0, ctypes.byref(wb)) == 0
+    pts = sum(s[0] ** 3 for s in insts)
+    assert bb.value >= 5 * 5 * pts * 8 + wb.value
+    assert L.nsf_batch_autotune_workspace_bytes(0, grids, 0, ctypes.byref(bb)) == nsf.EINVAL
+
+
+def test_autotune_rejects_a_small_workspace(nsf):
+    """Checked before any device work: a workspace below the query's size
+    is NSF_EWORKSPACE."""
+    L = nsf.lib()
+    g = nsf._grid((16, 16, 16))
+    phys = nsf._phys({"Re": 1600.0, "Ma": 0.1, "Pr": 0.71, "gamma": 1.4})
+    need = ctypes.c_size_t(0)
+    assert L.nsf_autotune_workspace_bytes(ctypes.byref(g), 0, 0, ctypes.byref(need)) == 0
+    r = nsf.TuneResult()
+    rc = L.nsf_autotune(ctypes.byref(g), ctypes.byref(phys), 0, 0, 1, None,
+                        ctypes.c_void_p(256), need.value - 1, ctypes.byref(r), None)
+    assert rc == nsf.EWORKSPACE
