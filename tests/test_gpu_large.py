@@ -1,7 +1,7 @@
 """GPU: the largest single-GPU grid, 1024^3 (2^30 points; the strong-scaling
-problem size of the paper's Section 4), in the fused SN form and in the
-stored-gradient SS form (whose separate update pass covers 5 * 2^30
-elements, more than one dispatch can address).
+problem size of the paper's Section 4): the residual of SN and RA, the fused
+SN step, and the stored-gradient SS form (whose separate update pass covers
+5 * 2^30 elements, more than one dispatch can address).
 
 Needs about 215 GB of device memory: q, q_acc and r (5 fields each) plus the
 work area (one rotating state sharing the primitive region, and a second).
@@ -37,10 +37,11 @@ def _room():
         pytest.skip(f"needs {need / 1e9:.0f} GB of free device memory, {free / 1e9:.0f} GB free")
 
 
-def test_1024_rhs_sampled_planes():
+@pytest.mark.parametrize("variant", ["SN", "RA"])
+def test_1024_rhs_sampled_planes(variant):
     _room()
-    print(f"case large RA fused {N}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "SN", "f64", tune=TUNE)
+    print(f"case large rhs {variant} {N}", flush=True)
+    s = nsf.Solver((N, N, N), PHYS, variant, "f64", tune=TUNE)
     s.init(W.tgv_pointwise(1610))
     s.rhs()
     torch.cuda.synchronize()
