@@ -623,6 +623,9 @@ constexpr int ring_slots() {
 // (the x-halo columns as whole 128-byte lines: 1.66x the algorithmic reads
 // of that kernel at 512^3). Double-precision 32 x 8 tiles drop the ring:
 // without its LDS two workgroups fit on a CU.
+#ifndef NSF_SS_HOIST
+#define NSF_SS_HOIST 1
+#endif
 #ifndef NSF_F64_Y8_HALO_RING
 #define NSF_F64_Y8_HALO_RING 0
 #endif
@@ -969,6 +972,28 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // at raised priority until it (double precision: -2.6% on the fused
         // 512^3 stage; single precision, which is bound by memory, gains
         // nothing)
+        // Stored-gradient form: the in-plane neighbours of the diagonal
+        // gradients (D_x of G_yy and G_zz, D_y of G_xx and G_zz) are fetched
+        // first thing in the iteration, so their latency overlaps the LDS
+        // writes and the barrier, and only their two sums stay live through
+        // the folds. (The full store set only: with the diagonal or in-plane
+        // sets the hoisted values push those kernels into spills.)
+        constexpr bool kHoistG = SS && !RC && GM == kGradAll && NSF_SS_HOIST;
+        T gnb[kHoistG ? 4 : 1][4];
+        if constexpr (kHoistG) {
+            const size_t pz = poff(z);
+            const int cx1 = GM == kGradAll ? 4 : gslot(1, 1);
+            const int cy0 = GM == kGradAll ? 0 : gslot(0, 0);
+            const int c22 = GM == kGradAll ? 8 : gslot(2, 2);
+            constexpr bool kZZ = GM == kGradAll || ((GM >> 8) & 1);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                gnb[0][m] = A.grad[cx1 * n + pz + xnb[m]];
+                gnb[1][m] = kZZ ? A.grad[c22 * n + pz + xnb[m]] : T(0);
+                gnb[2][m] = A.grad[cy0 * n + pz + ynb[m]];
+                gnb[3][m] = kZZ ? A.grad[c22 * n + pz + ynb[m]] : T(0);
+            }
+        }
         constexpr bool kHaloPrio = RP && sizeof(T) == 8;
         if constexpr (kHaloPrio) {
             if (tid < NHALO) __builtin_amdgcn_s_setprio(2);
@@ -1115,6 +1140,13 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
         // (c) leading-plane in-plane derivatives for the z cross terms
         if constexpr (!SS && !RC) leading(Vl, Xs[4], Xw[4], Yw[4], z + 2, true);
 
+        T crossxy[2] = {T(0), T(0)};
+        if constexpr (kHoistG) {
+            crossxy[0] = D1(gnb[0][0], gnb[0][1], gnb[0][2], gnb[0][3], k.a1[0], k.a2[0]) +
+                         D1(gnb[1][0], gnb[1][1], gnb[1][2], gnb[1][3], k.a1[0], k.a2[0]);
+            crossxy[1] = D1(gnb[2][0], gnb[2][1], gnb[2][2], gnb[2][3], k.a1[1], k.a2[1]) +
+                         D1(gnb[3][0], gnb[3][1], gnb[3][2], gnb[3][3], k.a1[1], k.a2[1]);
+        }
         // (d) residual at plane z
         const T* Vc = ring(z);
         const T uc[3] = {Vc[ownV], Vc[FOV + ownV], Vc[2 * FOV + ownV]};
@@ -1241,7 +1273,10 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             };
             // (a store set without G_zz belongs to a single-plane grid, where
             // every z difference, hence G_zz, is zero)
-            if constexpr (GM == kGradAll) {
+            if constexpr (kHoistG) {
+                cross[0] = crossxy[0];
+                cross[1] = crossxy[1];
+            } else if constexpr (GM == kGradAll) {
                 cross[0] = dxg(4) + dxg(8);
                 cross[1] = dyg(0) + dyg(8);
             } else {
