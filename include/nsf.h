@@ -283,16 +283,19 @@ int nsf_tune_get(const nsf_grid *g, int precision, nsf_tune_result *out);
 
 /* ---------------------------------------------------------------- batched form
  * Many independent Taylor-Green-type instances (own grid, parameters, dt)
- * advance together with the fused recompute-all stage: one persistent
- * launch per RK stage in which every workgroup runs its own run of
- * (instance, tile) items, taken from a schedule built once on the host (one
- * band of neighbouring tiles of equal cost per XCD, dealt longest first),
- * and the three stage launches of a step are captured once in a hipGraph. Each instance's q (precision dtype) and q_acc (double) are
- * caller-owned device buffers with the single-grid contract of nsf_rk_step;
- * `work` (nsf_batch_workspace_bytes) holds the other two stage states and
- * the diagnostics scratch of every instance and must stay allocated until
+ * advance together with a fused stage kernel (SN or RA): one persistent
+ * launch per RK stage in which the workgroups take (instance, tile) items
+ * from a list built once on the host (one band of neighbouring tiles of
+ * equal cost per XCD, longest first) through a device counter per band,
+ * and the three stage launches of a step are captured once in a hipGraph.
+ * Each instance's q (precision dtype) and q_acc (double) are caller-owned
+ * device buffers with the single-grid contract of nsf_rk_step; `work`
+ * (nsf_batch_workspace_bytes) holds the other two stage states and the
+ * diagnostics scratch of every instance and must stay allocated until
  * nsf_batch_destroy. The handle owns only the graph, a private capture
- * stream and the small device work list and schedule it allocates. */
+ * stream and the small device work list, band table and counters it
+ * allocates. Steps of one handle must not run concurrently (they share the
+ * counters, as they share the states). */
 typedef struct nsf_batch nsf_batch;
 
 int nsf_batch_workspace_bytes(int32_t count, const nsf_grid *grids, int precision, size_t *bytes);

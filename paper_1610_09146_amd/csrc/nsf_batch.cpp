@@ -29,8 +29,9 @@ struct nsf_batch {
     std::vector<double*> diag_partial;
     double* diag_out = nullptr;  // count * NSF_NDIAG doubles inside `work`
     void* desc_dev = nullptr;
-    int2* items_dev = nullptr;  // items in workgroup order
-    int* offs_dev = nullptr;     // workgroup b runs items [offs[b], offs[b+1])
+    int2* items_dev = nullptr;  // items, band by band (one band per XCD), longest first
+    int* boff_dev = nullptr;    // band x holds items [boff[x], boff[x+1])
+    int* ctr_dev = nullptr;     // per stage and band: the next item to take
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;      // one step, storing q_acc in its third substep
     hipGraphExec_t exec = nullptr;
@@ -76,21 +77,24 @@ int batch_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 48 : d
 // about three planes of the loop.
 constexpr int kWarmPlanes = 3;
 
-// Static schedule of the persistent stage launch. The item list (instances
-// in order, each one's tiles in launch order) is cut into one contiguous band
-// of equal cost per XCD, so the tiles that share halos run under one L2; each
-// band is then dealt to its XCD's workgroups longest item first, each item to
-// the least-loaded workgroup (longest-processing-time rule; the stable sort
-// keeps equal items in tile order, so neighbouring tiles still run together).
-// Workgroup b runs on XCD b mod 8 as the (b / 8)-th of its XCD. Against a
-// round-robin deal of the list this raises the mean per-workgroup load from
-// 87-89% to 93% of the largest on the 64-instance mix of sizes 32 to 128.
-void schedule_items(const std::vector<int2>& items, const std::vector<int>& cost, int nblocks,
-                    std::vector<int2>& order, std::vector<int>& offs) {
-    const int per = nblocks / kXCD;
+// Schedule of the persistent stage launch. The item list (instances in
+// order, each one's tiles in launch order) is cut into one contiguous band of
+// equal cost per XCD, so the tiles that share halos run under one L2; each
+// band is sorted longest item first (a stable sort: equal items stay in tile
+// order, so neighbouring tiles still run together). At run time the
+// workgroups of an XCD take their band's items in that order from a counter,
+// and a workgroup whose band is used up takes items from the next band:
+// longest-first dealing to whichever workgroup is free, which ends a stage
+// within about one short item of the mean load, where the static deal it
+// replaces left the busiest workgroup 6% above the mean on the 64-instance
+// mix (its 51-plane items outnumber what the short ones can even out within
+// a band).
+void schedule_items(const std::vector<int2>& items, const std::vector<int>& cost,
+                    std::vector<int2>& order, std::vector<int>& boff) {
     long long total = 0;
     for (int c : cost) total += c;
-    std::vector<std::vector<int>> lists(nblocks);
+    order.clear();
+    boff.assign(kXCD + 1, 0);
     size_t first = 0;
     long long run = 0;
     for (int x = 0; x < kXCD; ++x) {
@@ -104,22 +108,9 @@ void schedule_items(const std::vector<int2>& items, const std::vector<int>& cost
         std::vector<size_t> band;
         for (size_t i = first; i < last; ++i) band.push_back(i);
         std::stable_sort(band.begin(), band.end(), [&](size_t a, size_t c) { return cost[a] > cost[c]; });
-        using Load = std::pair<long long, int>;  // (load, index in the XCD)
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (int j = 0; j < per; ++j) heap.push({0, j});
-        for (size_t i : band) {
-            Load l = heap.top();
-            heap.pop();
-            lists[(size_t)l.second * kXCD + x].push_back((int)i);
-            heap.push({l.first + cost[i], l.second});
-        }
+        for (size_t i : band) order.push_back(items[i]);
+        boff[x + 1] = (int)order.size();
         first = last;
-    }
-    order.clear();
-    offs.assign(nblocks + 1, 0);
-    for (int b = 0; b < nblocks; ++b) {
-        for (int i : lists[b]) order.push_back(items[i]);
-        offs[b + 1] = (int)order.size();
     }
 }
 
@@ -160,17 +151,22 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
     b->diag_out = (double*)(work + off);
     b->nitems = (int)items.size();
     std::vector<int2> order;
-    std::vector<int> offs;
-    schedule_items(items, cost, b->nblocks, order, offs);
+    std::vector<int> boff;
+    schedule_items(items, cost, order, boff);
     hipError_t e = hipMalloc(&b->desc_dev, desc.size() * sizeof(BatchDesc<T>));
     if (e == hipSuccess) e = hipMalloc((void**)&b->items_dev, order.size() * sizeof(int2));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->offs_dev, offs.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->boff_dev, boff.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->ctr_dev, 3 * kXCD * sizeof(int));
     if (e == hipSuccess)
         e = hipMemcpy(b->desc_dev, desc.data(), desc.size() * sizeof(BatchDesc<T>), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->items_dev, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(b->offs_dev, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice);
+        e = hipMemcpy(b->boff_dev, boff.data(), boff.size() * sizeof(int), hipMemcpyHostToDevice);
+    // the stage counters start at zero; each stage launch then zeroes the
+    // next stage's (outside any graph: a synchronous set at creation)
+    if (e == hipSuccess) e = hipMemset(b->ctr_dev, 0, 3 * kXCD * sizeof(int));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) return bfail(NSF_EHIP, hipGetErrorString(e));
     return NSF_OK;
 }
@@ -178,8 +174,8 @@ int build_tables(nsf_batch* b, const std::vector<Dims>& dims, const nsf_phys* ph
 template <typename T>
 void enqueue_step(nsf_batch* b, hipStream_t s, int store_acc) {
     for (int st = 0; st < 3; ++st)
-        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->offs_dev, st,
-                           b->nblocks, b->tile_y, s, b->recompute != 0, store_acc);
+        launch_ra_batch<T>((const BatchDesc<T>*)b->desc_dev, b->items_dev, b->boff_dev, b->ctr_dev,
+                           st, b->nblocks, b->tile_y, s, b->recompute != 0, store_acc);
 }
 
 // whether the stage kernel can leave q_acc unwritten (see launch_ra_batch)
@@ -193,7 +189,8 @@ void release(nsf_batch* b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->desc_dev) (void)hipFree(b->desc_dev);
     if (b->items_dev) (void)hipFree(b->items_dev);
-    if (b->offs_dev) (void)hipFree(b->offs_dev);
+    if (b->boff_dev) (void)hipFree(b->boff_dev);
+    if (b->ctr_dev) (void)hipFree(b->ctr_dev);
     delete b;
 }
 

@@ -129,13 +129,17 @@ int default_zchunk(const Dims& d);
 int default_tile_y(int precision_bytes, const Dims& d);
 void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* tz, int* zc);
 // Persistent batched fused stage (recompute: RA, else SN): items[i] =
-// (instance, tile index), in workgroup order; workgroup b runs
-// items[offs[b]] .. items[offs[b + 1] - 1].
+// (instance, tile index), band by band; band x (items boff[x] ..
+// boff[x + 1] - 1) is taken in order by the workgroups of XCD x through the
+// counter ctr[stage * 8 + x], and then by any workgroup whose own band is
+// used up. ctr holds 3 * 8 ints, zero before a batch's first stage; each
+// stage launch zeroes the next stage's counters.
 // store_acc = 0 lets the double-precision 16-row form leave q_acc unwritten
 // in the third substep (every step but a call's last).
 template <typename T>
-void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
-                     int nblocks, int tile_y, hipStream_t s, bool recompute, int store_acc);
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* boff, int* ctr,
+                     int stage, int nblocks, int tile_y, hipStream_t s, bool recompute,
+                     int store_acc);
 template <typename T>
 int batch_blocks_per_cu(int tile_y, bool recompute);
 // Residual from stored primitives, no derivative arrays: recompute = true is

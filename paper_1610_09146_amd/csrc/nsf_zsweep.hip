@@ -1497,24 +1497,44 @@ k_ra_zsweep(ZArgs<T> A) {
                                                    sD, sM);
 }
 
-// Persistent batched stage kernel: workgroup b runs its own run of the
-// (instance, tile) items, items[offs[b]] .. items[offs[b + 1] - 1], from a
-// schedule built on the host (one band of neighbouring tiles per XCD, evened
-// out by item cost). Stage s reads state s of the rotation q -> qb -> qc -> q.
+// Persistent batched stage kernel: the workgroups take (instance, tile)
+// items from the host-built bands (one band of neighbouring tiles per XCD,
+// longest first) through one counter per band, each its own XCD's band
+// first. Every tile is computed the same way whichever workgroup runs it.
+// Stage s reads state s of the rotation q -> qb -> qc -> q.
 template <typename T, int TX, int TY, bool RC>
 __global__ void __attribute__((amdgpu_flat_work_group_size(TX * TY, TX * TY),
                                amdgpu_waves_per_eu(Occ<T, RC>::kWaves, Occ<T, RC>::kWaves)))
 k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items,
-           const int* __restrict__ offs, int stage, int store_acc) {
+           const int* __restrict__ boff, int* __restrict__ ctr, int stage, int store_acc) {
     using G = Geom<TX, TY>;
     __shared__ T sP[2 * kPF * G::NPL];
     __shared__ __attribute__((aligned(16))) T sV[ring_slots<T, TY, true, false, RC>() * 3 * G::NPL];
     __shared__ T sH[halo_ring<T, TY, true>() ? 2 * kPF * G::NHALO : 1];
     __shared__ T sD[d_ring<T, TY, false, RC>() ? 3 * G::DSZ : 1];
-    const int first = offs[blockIdx.x], last = offs[blockIdx.x + 1];
+    __shared__ int sItem;
     const double A_[2] = {2.0 / 3.0, 5.0 / 12.0};
     const double B_[3] = {1.0 / 4.0, 3.0 / 20.0, 3.0 / 5.0};
-    for (int i = first; i < last; ++i) {
+    // the next stage's counters are free (that stage last ran a full step
+    // ago and starts after this launch ends): zero them for it
+    if (blockIdx.x == 0 && threadIdx.x < kXCD) ctr[((stage + 1) % 3) * kXCD + threadIdx.x] = 0;
+    int* const c = ctr + stage * kXCD;
+    // this workgroup's XCD (dispatch deals workgroups to the XCDs in turn):
+    // its band first, then the following bands as they run out. A band is
+    // left after the first take past its end and never revisited, so every
+    // workgroup ends after at most (items it runs) + 8 takes.
+    int band = blockIdx.x % kXCD;
+    for (int tries = 0; tries < kXCD;) {
+        if (threadIdx.x == 0) sItem = atomicAdd(c + band, 1);
+        __syncthreads();
+        const int k = sItem;
+        __syncthreads();  // every thread has read sItem before the next take
+        const int i = boff[band] + k;
+        if (i >= boff[band + 1]) {
+            band = (band + 1) % kXCD;
+            ++tries;
+            continue;
+        }
         const int2 it = items[i];
         const BatchDesc<T>& bd = desc[it.x];
         ZArgs<T> A;
@@ -1652,23 +1672,24 @@ void launch_ss_fused(const Dims& d, const Coef<T>& c, const T* q, const T* prim,
 }
 
 template <typename T>
-void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* offs, int stage,
-                     int nblocks, int tile_y, hipStream_t s, bool recompute, int store_acc) {
+void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* boff, int* ctr,
+                     int stage, int nblocks, int tile_y, hipStream_t s, bool recompute,
+                     int store_acc) {
     TimerScope ts("ra_batch", s);
     const dim3 g(nblocks);
     if (recompute) {
         if (tile_y == 16)
             hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, true>), g, dim3(kTX * 16), 0, s, desc, items,
-                               offs, stage, store_acc);
+                               boff, ctr, stage, store_acc);
         else
             hipLaunchKernelGGL((k_ra_batch<T, kTX, 8, true>), g, dim3(kTX * 8), 0, s, desc, items,
-                               offs, stage, store_acc);
+                               boff, ctr, stage, store_acc);
     } else if (tile_y == 16) {
         hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, false>), g, dim3(kTX * 16), 0, s, desc, items,
-                           offs, stage, store_acc);
+                           boff, ctr, stage, store_acc);
     } else {
         hipLaunchKernelGGL((k_ra_batch<T, kTX, 8, false>), g, dim3(kTX * 8), 0, s, desc, items,
-                           offs, stage, store_acc);
+                           boff, ctr, stage, store_acc);
     }
 }
 
@@ -1749,8 +1770,8 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
 }
 
 #define NSF_INST(T)                                                                          \
-    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, const int*, int, int, int, \
-                                     hipStream_t, bool, int);                                 \
+    template void launch_ra_batch<T>(const BatchDesc<T>*, const int2*, const int*, int*, int,    \
+                                     int, int, hipStream_t, bool, int);                       \
     template int batch_blocks_per_cu<T>(int, bool);                                           \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
                                       int, int, hipStream_t, bool);                         \
