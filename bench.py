@@ -41,16 +41,17 @@ FAMILY_BYTES = {
     "ra_zsweep": (120, 60),       # RA: q, prims -> r
     "sn_zsweep": (120, 60),       # SN: q, prims -> r
     # fused stages. Double precision: the first substep reads the
-    # accumulator from q (equal at a step boundary): q -> q_next, q_acc; a
-    # third substep other than a call's last leaves q_acc unwritten:
-    # q, q_acc -> q_next
+    # accumulator from q (equal at a step boundary) and stores none: q ->
+    # q_next; the second forms that accumulator from the step's initial state
+    # and reads it in place of q_acc (160 B as before); a third substep other
+    # than a call's last leaves q_acc unwritten: q, q_acc -> q_next
     "ra_fused": (160, 120),       # RA: q, q_acc -> q_next, q_acc
-    "ra_fused_mon": (120, 120),   # RA first substep, plus per-tile KE / enstrophy sums
-    "ra_fused_first": (120, 120),  # RA first substep, unmonitored
+    "ra_fused_mon": (80, 120),    # RA first substep, plus per-tile KE / enstrophy sums
+    "ra_fused_first": (80, 120),  # RA first substep, unmonitored
     "ra_fused_last": (120, 120),  # RA third substep without the q_acc store
     "sn_fused": (160, 120),       # SN: q, q_acc -> q_next, q_acc
-    "sn_fused_mon": (120, 120),   # SN first substep, plus per-tile KE / enstrophy sums
-    "sn_fused_first": (120, 120),  # SN first substep, unmonitored
+    "sn_fused_mon": (80, 120),    # SN first substep, plus per-tile KE / enstrophy sums
+    "sn_fused_first": (80, 120),  # SN first substep, unmonitored
     "sn_fused_last": (120, 120),  # SN third substep without the q_acc store
     "rs_zsweep": (192, 96),       # RS: q, prims, 9 gradients -> r
     "ss_grad_naive": (96, 48),    # u, v, w -> 9 gradients
@@ -205,7 +206,8 @@ def run_batch(nsf, torch, W, precision, steps, warmup=1):
     nitems, nblocks = b.info()
     # algorithmic bytes per point and step of the batched stages: in double
     # precision with 16-row tiles the first substep reads the accumulator
-    # from q and the third leaves it unwritten (but in a call's last step)
+    # from q and stores none, and the third leaves it unwritten (but in a
+    # call's last step)
     cfg = b.config()
     if precision == "f64" and cfg["tile_y"] == 16:
         per_pt = (FAMILY_BYTES["sn_fused_first"][0] + FAMILY_BYTES["sn_fused"][0]

@@ -364,11 +364,18 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.last = st == 2;
                 // double precision: the state and the accumulator are equal at
                 // a step boundary, so the first substep reads the accumulator
-                // from q, and only the call's last step stores q_acc in its
+                // from q and stores none (the second forms the first's
+                // accumulator, q0 + B_1 dt R_1, as q0 + (B_1 / A_1)(q1 - q0)
+                // from the step's initial state, still in q, and its own
+                // input), and only the call's last step stores q_acc in its
                 // third substep (the next step reads the state from q)
                 if (sizeof(T) == 8) {
                     sc.acc_from_q = st == 0;
-                    sc.store_acc = st < 2 || step == nsteps - 1;
+                    sc.store_acc = st == 1 || (st == 2 && step == nsteps - 1);
+                    if (st == 1) {
+                        sc.acc_src = q;
+                        sc.acc_mix = B[0] / A[0];
+                    }
                 }
                 const bool mon = monitor && st == 0;
                 launch_ra_fused<T>(d, c, in[st], out[st], qacc, sc, zc, ty, s,

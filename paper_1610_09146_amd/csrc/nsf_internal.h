@@ -29,11 +29,16 @@ struct StageCoef {
     double b_dt;  // B_s dt
     int last;     // 1 on the third substep: q = q_acc after the update
     // Double-precision fused stages only: the first substep reads the
-    // accumulator from the state q (equal to q_acc at a step boundary), and a
-    // third substep other than the call's last leaves q_acc unwritten (its
+    // accumulator from the state q (equal to q_acc at a step boundary) and
+    // leaves q_acc unwritten; the second forms the accumulator of the first,
+    // q0 + B_1 dt R_1 = q0 + (B_1 / A_1)(q1 - q0), from the step's initial
+    // state q0 (read from acc_src) and its own input q1 (acc_mix = B_1 / A_1);
+    // a third substep other than the call's last leaves q_acc unwritten (its
     // value is the state the next step's first substep reads from q).
     int acc_from_q = 0;
     int store_acc = 1;
+    const void* acc_src = nullptr;
+    double acc_mix = 0.0;
 };
 
 // Record an error message for nsf_last_error() and return `code`.
@@ -100,6 +105,9 @@ struct ZArgs {
     double* qacc;
     const double* qacc_in;  // where the fused stage reads the accumulator (qacc, or q)
     int acc_store;          // fused stage: 0 leaves q_acc unwritten
+    // fused stage: the accumulator used is acc + acc_mix * (q_own - acc),
+    // q_own the stage input at the point (0 = acc itself)
+    double acc_mix;
     double a_dt, b_dt;
     int last;
     int zchunk, tiles_x, tiles_y;

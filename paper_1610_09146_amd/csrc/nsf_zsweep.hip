@@ -1350,8 +1350,16 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
             const uint32_t pbT = (uint32_t)(plane * sizeof(T));
             const uint32_t offT = active ? (uint32_t)(col * sizeof(T)) : kOutside;
             if constexpr (kAccAhead) {
+                // the second substep's accumulator from the step's initial
+                // state (accN) and its own input state at the point: q0 +
+                // (B_1 / A_1)(q1 - q0), which is q0 + B_1 dt R_1 (the first
+                // substep stores no accumulator); acc_mix = 0 elsewhere, and
+                // fma(0, x, a) = a
+                const double rho1 = (double)Qz[2].rho;
+                const double q1[5] = {rho1, rho1 * uc[0], rho1 * uc[1], rho1 * uc[2],
+                                      (double)Qz[2].E};
 #pragma unroll
-                for (int f = 0; f < 5; ++f) acc[f] = accN[f];
+                for (int f = 0; f < 5; ++f) acc[f] = fma(A.acc_mix, q1[f] - accN[f], accN[f]);
             } else if constexpr (!kEarlyAcc) {
 #pragma unroll
                 for (int f = 0; f < 5; ++f) acc[f] = view_load(plane_view(A.qacc + f * n + zo, pb), off);
@@ -1547,11 +1555,14 @@ k_ra_batch(const BatchDesc<T>* __restrict__ desc, const int2* __restrict__ items
         A.r = nullptr;
         A.qacc = bd.qacc;
         // double precision, 16-row tiles: the first substep reads the
-        // accumulator from q (equal at a step boundary), and the third
-        // leaves q_acc unwritten unless store_acc (the last step of a call)
+        // accumulator from q (equal at a step boundary) and leaves q_acc
+        // unwritten, the second forms the first's accumulator from the
+        // step's initial state, still in q (see ZArgs::acc_mix), and the
+        // third leaves q_acc unwritten unless store_acc (a call's last step)
         constexpr bool kSave = sizeof(T) == 8 && TY == 16;
-        A.qacc_in = (kSave && stage == 0) ? reinterpret_cast<const double*>(bd.q) : bd.qacc;
-        A.acc_store = (kSave && stage == 2) ? store_acc : 1;
+        A.qacc_in = (kSave && stage < 2) ? reinterpret_cast<const double*>(bd.q) : bd.qacc;
+        A.acc_store = kSave ? (stage == 0 ? 0 : stage == 2 ? store_acc : 1) : 1;
+        A.acc_mix = (kSave && stage == 1) ? B_[0] / A_[0] : 0.0;
         A.a_dt = stage < 2 ? A_[stage] * bd.dt : 0.0;
         A.b_dt = B_[stage] * bd.dt;
         A.last = stage == 2;
@@ -1729,7 +1740,7 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     // equals q at a step boundary, and the value stored is the new state).
     const bool saving = sizeof(T) == 8 && tile_y == 16;
     const bool first_q = saving && sc.acc_from_q;
-    const bool last_ns = saving && !sc.store_acc;
+    const bool last_ns = saving && !sc.store_acc && !sc.acc_from_q;
     // timer families by what a launch moves: the monitored first substep,
     // an unmonitored first substep that reads the accumulator from q, a
     // third substep that leaves q_acc unwritten, and the full stage
@@ -1747,8 +1758,10 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.qacc = qacc;
     // the first substep may read the accumulator from the state (double
     // precision only: there q_acc equals q at a step boundary)
-    a.qacc_in = first_q ? reinterpret_cast<const double*>(q) : qacc;
-    a.acc_store = last_ns ? 0 : 1;
+    a.qacc_in = first_q ? reinterpret_cast<const double*>(q)
+                : (saving && sc.acc_src) ? reinterpret_cast<const double*>(sc.acc_src) : qacc;
+    a.acc_store = saving && !sc.store_acc ? 0 : 1;
+    a.acc_mix = saving ? sc.acc_mix : 0.0;
     a.a_dt = sc.a_dt;
     a.b_dt = sc.b_dt;
     a.last = sc.last;
