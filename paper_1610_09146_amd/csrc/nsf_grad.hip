@@ -5,17 +5,27 @@
 // order of 3a + b: all nine (the paper's 3D set), the three diagonal ones,
 // or the four in-plane ones of a two-dimensional grid (the paper's 2D
 // count). z-marching tiles: the velocity of each plane (with a two-point x-y
-// halo), formed from q, enters a five-plane LDS ring once; x, y and z
-// differences of the centre plane are taken from the ring.
+// halo), formed from q, enters a four-plane LDS ring once; x and y
+// differences of the centre plane are taken from the ring, z differences
+// from a register queue of the own column.
 #include "nsf_internal.h"
 
 namespace nsf {
 
 namespace {
 
-constexpr int kTX = 32, kTY = 8, kNT = kTX * kTY;
-constexpr int kLX = kTX + 4, kLY = kTY + 4, kNPL = kLX * kLY, kNHALO = kNPL - kNT;
-constexpr int kRing = 5;
+// Tile shape: 32 x TY points, one thread per point of a plane.
+template <int TY>
+struct PgTile {
+    static constexpr int TX = 32, NT = TX * TY;
+    static constexpr int LX = TX + 4, LY = TY + 4, NPL = LX * LY, NHALO = NPL - NT;
+    static_assert(NHALO <= NT, "one halo point per thread at most");
+};
+// LDS velocity ring: planes z .. z+2 are in use at iteration z, and the slot
+// that plane z+2 enters was last read two iterations before (every thread has
+// passed the barrier of the iteration between), so four slots need one
+// barrier per plane
+constexpr int kRing = 4;
 constexpr int kXCD = 8;
 
 __device__ __forceinline__ int pmodg(int a, int n) {
@@ -29,20 +39,22 @@ __device__ __forceinline__ int xcd_tile_g(int bid, int nb) {
     return x * per + (x < extra ? x : extra) + k;
 }
 
+template <int TY>
 __device__ __forceinline__ void halo_pos_g(int h, int& hx, int& hy) {
-    constexpr int ROWS2 = 2 * kLX;
+    using G = PgTile<TY>;
+    constexpr int ROWS2 = 2 * G::LX;
     if (h < ROWS2) {
-        hy = h / kLX;
-        hx = h % kLX;
+        hy = h / G::LX;
+        hx = h % G::LX;
     } else if (h < 2 * ROWS2) {
         const int t = h - ROWS2;
-        hy = kTY + 2 + t / kLX;
-        hx = t % kLX;
+        hy = TY + 2 + t / G::LX;
+        hx = t % G::LX;
     } else {
         const int t = h - 2 * ROWS2;
         hy = 2 + t / 4;
         const int c = t % 4;
-        hx = c < 2 ? c : kTX + c;
+        hx = c < 2 ? c : G::TX + c;
     }
 }
 
@@ -58,11 +70,15 @@ struct GradArgs {
 // primitive loop's arithmetic, so the stored values are the same bits) and
 // the velocity of its halo points, and writes the primitives of the chunk's
 // planes beside the store set's gradients. 152 bytes per point (double)
-// instead of the 80 + 96 of the two loops.
-template <typename T, int GM>
-__global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* __restrict__ q,
-                                                       T* __restrict__ prim,
-                                                       T* __restrict__ grad) {
+// instead of the 80 + 96 of the two loops. The in-plane differences of the
+// centre plane come from the LDS ring, the z differences from a register
+// queue of the own column's velocity (planes z-2 .. z+2).
+template <typename T, int GM, int TY>
+__global__ void __launch_bounds__(32 * TY) k_ss_prims_grad(GradArgs<T> A, const T* __restrict__ q,
+                                                           T* __restrict__ prim,
+                                                           T* __restrict__ grad) {
+    using G = PgTile<TY>;
+    constexpr int kTX = G::TX, kLX = G::LX, kNPL = G::NPL, kNHALO = G::NHALO;
     auto slot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
     auto stored = [](int a, int b) { return (GM >> (3 * a + b)) & 1; };
     __shared__ T sV[kRing * 3 * kNPL];
@@ -74,7 +90,7 @@ __global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* _
     const int tix = t % A.tiles_x;
     const int tiy = (t / A.tiles_x) % A.tiles_y;
     const int tiz = t / (A.tiles_x * A.tiles_y);
-    const int x0 = tix * kTX, y0 = tiy * kTY, z0 = tiz * A.zchunk;
+    const int x0 = tix * kTX, y0 = tiy * TY, z0 = tiz * A.zchunk;
     const int z1 = min(z0 + A.zchunk, d.nz);
     const int tid = threadIdx.x;
     const int lx = tid % kTX, ly = tid / kTX;
@@ -86,7 +102,7 @@ __global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* _
     size_t hcol = 0;
     if (hval) {
         int hx, hy;
-        halo_pos_g(tid, hx, hy);
+        halo_pos_g<TY>(tid, hx, hy);
         hidx = hy * kLX + hx;
         hcol = (size_t)pmodg(y0 + hy - 2, d.ny) * d.nx + pmodg(x0 + hx - 2, d.nx);
     }
@@ -104,15 +120,18 @@ __global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* _
 #pragma unroll
         for (int f = 0; f < 4; ++f) r.own[f] = q[f * n + po + col];
         r.own[4] = ld_nt(q + 4 * n + po + col);
-        if (hval)
 #pragma unroll
-            for (int f = 0; f < 4; ++f) r.halo[f] = q[f * n + po + hcol];
+        for (int f = 0; f < 4; ++f) r.halo[f] = hval ? q[f * n + po + hcol] : T(1);
         return r;
     };
-    // velocity into the ring; the primitives of the chunk's own planes out
-    auto enter = [&](int zz, const Raw& r) {
+    // velocity of plane zz into its ring slot and the own column's queue
+    // entry vq; the primitives of the chunk's own planes out
+    auto enter = [&](int zz, const Raw& r, T vq[3]) {
         T* V = sV + pmodg(zz, kRing) * 3 * kNPL;
         const Prim<T> P = primitives(r.own[0], r.own[1], r.own[2], r.own[3], r.own[4], c);
+        vq[0] = P.u;
+        vq[1] = P.v;
+        vq[2] = P.w;
         V[own] = P.u;
         V[kNPL + own] = P.v;
         V[2 * kNPL + own] = P.w;
@@ -131,22 +150,24 @@ __global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* _
             st_nt(P.t, prim + 4 * n + o);
         }
     };
-    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s));
+    T vq[5][3];  // own column's velocity, planes z-2 .. z+2
+#pragma unroll
+    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s), vq[s + 1]);
     Raw nxt = fetch(z0 + 2);
     const T a1x = c.a1[0], a2x = c.a2[0], a1y = c.a1[1], a2y = c.a2[1];
     const T a1z = c.a1[2], a2z = c.a2[2];
     for (int z = z0; z < z1; ++z) {
         const Raw cur = nxt;
         if (z + 1 < z1) nxt = fetch(z + 3);
-        enter(z + 2, cur);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) vq[s][a] = vq[s + 1][a];
+        enter(z + 2, cur, vq[4]);
         __syncthreads();
         if (active) {
             const size_t o = (size_t)z * plane + col;
             const T* Vc = sV + pmodg(z, kRing) * 3 * kNPL;
-            const T* Vm2 = sV + pmodg(z - 2, kRing) * 3 * kNPL;
-            const T* Vm1 = sV + pmodg(z - 1, kRing) * 3 * kNPL;
-            const T* Vp1 = sV + pmodg(z + 1, kRing) * 3 * kNPL;
-            const T* Vp2 = sV + pmodg(z + 2, kRing) * 3 * kNPL;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const T* F = Vc + a * kNPL;
@@ -157,35 +178,57 @@ __global__ void __launch_bounds__(kNT) k_ss_prims_grad(GradArgs<T> A, const T* _
                     st_nt(a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]),
                           grad + slot(a, 1) * n + o);
                 if (stored(a, 2))
-                    st_nt(a1z * (Vp1[a * kNPL + own] - Vm1[a * kNPL + own]) +
-                              a2z * (Vp2[a * kNPL + own] - Vm2[a * kNPL + own]),
+                    st_nt(a1z * (vq[3][a] - vq[1][a]) + a2z * (vq[4][a] - vq[0][a]),
                           grad + slot(a, 2) * n + o);
             }
         }
-        __syncthreads();
     }
 }
 
 }  // namespace
 
+template <typename T, int TY>
+static void launch_pg(const GradArgs<T>& a, int gmask, const T* q, T* prim, T* grad,
+                      hipStream_t s) {
+    const int tz = (a.d.nz + a.zchunk - 1) / a.zchunk;
+    const dim3 grid(a.tiles_x * a.tiles_y * tz), block(32 * TY);
+    if (gmask == kGradDiag)
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradDiag, TY>), grid, block, 0, s, a, q, prim, grad);
+    else if (gmask == kGradPlane)
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradPlane, TY>), grid, block, 0, s, a, q, prim, grad);
+    else
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradAll, TY>), grid, block, 0, s, a, q, prim, grad);
+}
+
+// Tiles: on large grids 32 x 32 with 128-plane chunks, while that leaves four
+// tiles per CU (one workgroup each: its four-plane ring takes 124 KB in
+// double precision). Their halo and chunk preamble re-read q 1.13 times at
+// 512^3, against 1.44 times for 32 x 16 tiles with 64-plane chunks (3.90
+// against 4.12 ms per launch). Smaller grids keep 32 x 8 tiles (three
+// workgroups per CU) with chunks of at most 64 planes, halved down to 16
+// while the grid has fewer tiles than the GPU has CUs (256^3: 0.53 ms
+// against 0.55 ms for the large tiles; 128^3: 32-plane chunks, 0.074 ms
+// against 0.101 ms for 64).
 template <typename T>
 void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
                           int gmask, hipStream_t s) {
     TimerScope ts("ss_prims_grad", s);
+    constexpr int kCUs = 256;
     GradArgs<T> a;
     a.d = d;
     a.c = c;
-    a.zchunk = d.nz >= 64 ? 64 : d.nz;
-    a.tiles_x = (d.nx + kTX - 1) / kTX;
-    a.tiles_y = (d.ny + kTY - 1) / kTY;
-    const int tz = (d.nz + a.zchunk - 1) / a.zchunk;
-    const dim3 grid(a.tiles_x * a.tiles_y * tz);
-    if (gmask == kGradDiag)
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradDiag>), grid, dim3(kNT), 0, s, a, q, prim, grad);
-    else if (gmask == kGradPlane)
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradPlane>), grid, dim3(kNT), 0, s, a, q, prim, grad);
-    else
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradAll>), grid, dim3(kNT), 0, s, a, q, prim, grad);
+    a.tiles_x = (d.nx + 31) / 32;
+    if (a.tiles_x * ((d.ny + 31) / 32) * (d.nz / 128) >= 4 * kCUs) {
+        a.tiles_y = (d.ny + 31) / 32;
+        a.zchunk = 128;
+        launch_pg<T, 32>(a, gmask, q, prim, grad, s);
+    } else {
+        a.tiles_y = (d.ny + 7) / 8;
+        int zc = 64;
+        while (zc > 16 && a.tiles_x * a.tiles_y * ((d.nz + zc - 1) / zc) < kCUs) zc /= 2;
+        a.zchunk = d.nz < zc ? d.nz : zc;
+        launch_pg<T, 8>(a, gmask, q, prim, grad, s);
+    }
 }
 
 template void launch_ss_prims_grad<float>(const Dims&, const Coef<float>&, const float*, float*,

@@ -5,7 +5,8 @@ double precision with 32 x 16 tiles and in the single-precision form with
 32 x 8 tiles, 64-plane z-chunks (Section 2 time loop, Section 3 set-up);
 and at 256^3 (dt = 8.4625e-4) the monitored step of each algorithm the
 benchmark compares there (BL, RA, RS, SN, SS with stored primitives, and
-the fused RA).
+the fused RA and SS), and at 512^3 the stored-gradient forms (the fused SS
+stage and RS) in the tiling the benchmark times.
 
 The oracle cannot advance 2^27 points in seconds, but a step's result on a
 few z-planes depends only on six planes either side of them, so sampled
@@ -100,7 +101,18 @@ def test_512_monitored_fused_step_f32_form_sampled_planes():
 def test_256_monitored_step_sampled_planes(variant, tune):
     # the 256^3 comparison of the algorithms (pointwise +-1e-3, seed 1610,
     # dt = 8.4625e-4): each variant's monitored step at its default tuning
-    n = 256
+    _monitored_step_sampled_planes(variant, tune, 256)
+
+
+@pytest.mark.parametrize("variant,tune", [("SS", {"fuse": 1}), ("RS", None)])
+def test_512_stored_gradient_step_sampled_planes(variant, tune):
+    # the stored-gradient forms as the benchmark times them at 512^3, where
+    # their primitive and gradient kernel takes its large tiles (32 x 32,
+    # 128-plane chunks; the middle sample straddles the chunk seam at 256)
+    _monitored_step_sampled_planes(variant, tune, 512)
+
+
+def _monitored_step_sampled_planes(variant, tune, n):
     print(f"case fullsize monitored step {variant} {tune} {n}", flush=True)
     s = nsf.Solver((n, n, n), PHYS, variant, "f64", tune=tune)
     s.init(W.tgv_pointwise(1610))
