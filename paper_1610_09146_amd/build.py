@@ -19,7 +19,16 @@ LIB = os.path.join(HERE, "libnsf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["nsf_api.cpp", "nsf_pointwise.hip", "nsf_naive.hip", "nsf_bl.hip", "nsf_diag.hip",
-           "nsf_zsweep.hip", "nsf_batch.cpp", "nsf_grad.hip", "nsf_tune.cpp"]
+           "nsf_zsweep.hip", "nsf_zsweep_rc.hip", "nsf_batch.cpp", "nsf_grad.hip",
+           "nsf_tune.cpp"]
+
+# Per-unit flags. The z-marching kernels without recomputation (SN, SS,
+# their fused stages and the batched SN stage) are scheduled with the AMDGPU
+# register-pressure trackers: same instructions, a schedule that runs the
+# fused SN stage about 1% and the fused SS stage about 7% faster at 512^3.
+# The recompute forms (nsf_zsweep_rc.hip) keep the default, under which they
+# do not spill.
+UNIT_FLAGS = {"nsf_zsweep.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"]}
 
 CFLAGS = [
     "-x", "hip", "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -31,7 +40,7 @@ CFLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *UNIT_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

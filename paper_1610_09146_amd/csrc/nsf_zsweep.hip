@@ -1454,6 +1454,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     }
 }
 
+#ifndef NSF_ZSWEEP_RC_UNIT
 // One block folds the per-tile monitor sums in tile order.
 __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict__ mpart, int ntiles,
                                                       double inv_n, double* __restrict__ out2) {
@@ -1483,6 +1484,7 @@ __global__ void __launch_bounds__(256) k_monitor_final(const double* __restrict_
         out2[1] = y * inv_n;
     }
 }
+#endif
 
 // Waves per SIMD the register budget is tuned for: double-precision tiles
 // need up to 256 VGPRs (two waves), single precision fits three.
@@ -1590,6 +1592,65 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
 
 }  // namespace
 
+// The recompute instantiations (RA, RS) are compiled in a unit of their own
+// (nsf_zsweep_rc.hip includes this file with NSF_ZSWEEP_RC_UNIT defined), so
+// that each unit can take the scheduler setting that suits its kernels: the
+// other forms are scheduled with the AMDGPU register-pressure trackers
+// (-1% on the fused SN stage, -7% on the fused SS stage at 512^3), which
+// make the recompute tiles spill (80 B per lane in the fused RA stage, +21%).
+template <typename T, int TY, bool FUSED, bool SS, bool MON, int GM>
+void launch_tiles_rc(const ZArgs<T>& a, int zchunk, hipStream_t s);
+template <typename T, int TY>
+void launch_batch_rc(dim3 g, const BatchDesc<T>* desc, const int2* items, const int* boff,
+                     int* ctr, int stage, int store_acc, hipStream_t s);
+template <typename T, int TY>
+hipError_t batch_occupancy_rc(int* nb);
+
+#ifdef NSF_ZSWEEP_RC_UNIT
+
+template <typename T, int TY, bool FUSED, bool SS, bool MON, int GM>
+void launch_tiles_rc(const ZArgs<T>& a, int zchunk, hipStream_t s) {
+    launch_tiles<T, kTX, TY, FUSED, SS, MON, true, GM>(a, zchunk, s);
+}
+
+template <typename T, int TY>
+void launch_batch_rc(dim3 g, const BatchDesc<T>* desc, const int2* items, const int* boff,
+                     int* ctr, int stage, int store_acc, hipStream_t s) {
+    hipLaunchKernelGGL((k_ra_batch<T, kTX, TY, true>), g, dim3(kTX * TY), 0, s, desc, items, boff,
+                       ctr, stage, store_acc);
+}
+
+template <typename T, int TY>
+hipError_t batch_occupancy_rc(int* nb) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_ra_batch<T, kTX, TY, true>,
+                                                        kTX * TY, 0);
+}
+
+// RA residual, fused RA stage (monitored or not), RS residual per store set
+#define NSF_RC_INST(T, TY)                                                                      \
+    template void launch_tiles_rc<T, TY, false, false, false, kGradAll>(const ZArgs<T>&, int,    \
+                                                                        hipStream_t);           \
+    template void launch_tiles_rc<T, TY, true, false, true, kGradAll>(const ZArgs<T>&, int,      \
+                                                                      hipStream_t);             \
+    template void launch_tiles_rc<T, TY, true, false, false, kGradAll>(const ZArgs<T>&, int,     \
+                                                                       hipStream_t);            \
+    template void launch_tiles_rc<T, TY, false, true, false, kGradAll>(const ZArgs<T>&, int,     \
+                                                                       hipStream_t);            \
+    template void launch_tiles_rc<T, TY, false, true, false, kGradDiag>(const ZArgs<T>&, int,    \
+                                                                        hipStream_t);           \
+    template void launch_tiles_rc<T, TY, false, true, false, kGradPlane>(const ZArgs<T>&, int,   \
+                                                                         hipStream_t);          \
+    template void launch_batch_rc<T, TY>(dim3, const BatchDesc<T>*, const int2*, const int*,     \
+                                         int*, int, int, hipStream_t);                          \
+    template hipError_t batch_occupancy_rc<T, TY>(int*);
+NSF_RC_INST(float, 8)
+NSF_RC_INST(float, 16)
+NSF_RC_INST(double, 8)
+NSF_RC_INST(double, 16)
+#undef NSF_RC_INST
+
+#else  // the unit of every other form and the launchers
+
 int default_zchunk(const Dims& d) { return d.nz >= 256 ? 64 : (d.nz >= 64 ? 32 : d.nz); }
 
 // Double precision: 32 x 16 tiles (one 512-thread workgroup per CU, fewest
@@ -1618,8 +1679,8 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.prim = prim;
     a.r = r;
     if (recompute) {
-        if (tile_y == 16) launch_tiles<T, kTX, 16, false, false, false, true>(a, zchunk, s);
-        else launch_tiles<T, kTX, 8, false, false, false, true>(a, zchunk, s);
+        if (tile_y == 16) launch_tiles_rc<T, 16, false, false, false, kGradAll>(a, zchunk, s);
+        else launch_tiles_rc<T, 8, false, false, false, kGradAll>(a, zchunk, s);
     } else {
         if (tile_y == 16) launch_tiles<T, kTX, 16, false>(a, zchunk, s);
         else launch_tiles<T, kTX, 8, false>(a, zchunk, s);
@@ -1629,8 +1690,8 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
 template <typename T, int GM>
 void launch_ss_set(const ZArgs<T>& a, int zchunk, int tile_y, hipStream_t s, bool recompute) {
     if (recompute) {
-        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, true, GM>(a, zchunk, s);
-        else launch_tiles<T, kTX, 8, false, true, false, true, GM>(a, zchunk, s);
+        if (tile_y == 16) launch_tiles_rc<T, 16, false, true, false, GM>(a, zchunk, s);
+        else launch_tiles_rc<T, 8, false, true, false, GM>(a, zchunk, s);
     } else {
         if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, false, GM>(a, zchunk, s);
         else launch_tiles<T, kTX, 8, false, true, false, false, GM>(a, zchunk, s);
@@ -1689,12 +1750,8 @@ void launch_ra_batch(const BatchDesc<T>* desc, const int2* items, const int* bof
     TimerScope ts("ra_batch", s);
     const dim3 g(nblocks);
     if (recompute) {
-        if (tile_y == 16)
-            hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, true>), g, dim3(kTX * 16), 0, s, desc, items,
-                               boff, ctr, stage, store_acc);
-        else
-            hipLaunchKernelGGL((k_ra_batch<T, kTX, 8, true>), g, dim3(kTX * 8), 0, s, desc, items,
-                               boff, ctr, stage, store_acc);
+        if (tile_y == 16) launch_batch_rc<T, 16>(g, desc, items, boff, ctr, stage, store_acc, s);
+        else launch_batch_rc<T, 8>(g, desc, items, boff, ctr, stage, store_acc, s);
     } else if (tile_y == 16) {
         hipLaunchKernelGGL((k_ra_batch<T, kTX, 16, false>), g, dim3(kTX * 16), 0, s, desc, items,
                            boff, ctr, stage, store_acc);
@@ -1709,9 +1766,7 @@ int batch_blocks_per_cu(int tile_y, bool recompute) {
     int nb = 0;
     hipError_t e;
     if (recompute)
-        e = tile_y == 16
-            ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16, true>, kTX * 16, 0)
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 8, true>, kTX * 8, 0);
+        e = tile_y == 16 ? batch_occupancy_rc<T, 16>(&nb) : batch_occupancy_rc<T, 8>(&nb);
     else
         e = tile_y == 16
             ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ra_batch<T, kTX, 16, false>, kTX * 16, 0)
@@ -1767,11 +1822,11 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
     a.last = sc.last;
     if (recompute) {
         if (mpart) {
-            if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, true, true>(a, zchunk, s);
-            else launch_tiles<T, kTX, 8, true, false, true, true>(a, zchunk, s);
+            if (tile_y == 16) launch_tiles_rc<T, 16, true, false, true, kGradAll>(a, zchunk, s);
+            else launch_tiles_rc<T, 8, true, false, true, kGradAll>(a, zchunk, s);
         } else {
-            if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, false, true>(a, zchunk, s);
-            else launch_tiles<T, kTX, 8, true, false, false, true>(a, zchunk, s);
+            if (tile_y == 16) launch_tiles_rc<T, 16, true, false, false, kGradAll>(a, zchunk, s);
+            else launch_tiles_rc<T, 8, true, false, false, kGradAll>(a, zchunk, s);
         }
     } else if (mpart) {
         if (tile_y == 16) launch_tiles<T, kTX, 16, true, false, true>(a, zchunk, s);
@@ -1798,5 +1853,7 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
 NSF_INST(float)
 NSF_INST(double)
 #undef NSF_INST
+
+#endif  // NSF_ZSWEEP_RC_UNIT
 
 }  // namespace nsf
