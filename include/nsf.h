@@ -175,11 +175,13 @@ int nsf_rhs(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
  * then q = q_acc; A = (2/3, 5/12), B = (1/4, 3/20, 3/5).
  * On entry q_acc must hold the state (double) and q its value in the
  * precision dtype; on return both hold the new state. (In double precision
- * the two are then equal, and the fused form uses that: its first substep
- * reads the accumulator from q and writes none, its second forms the first's
- * accumulator as q0 + (B_1 / A_1)(q1 - q0) from the step's initial state q0
- * and its own input q1, and its third substep writes q_acc only in the
- * call's last step.) r is a 5-field scratch in the precision dtype.
+ * the two are then equal, and the fused SN and RA stages with 16-row tiles
+ * use that, with results equal up to one rounding of the accumulator: the
+ * first substep reads the accumulator from q and writes none, the second
+ * forms the first's accumulator as q0 + (B_1 / A_1)(q1 - q0) from the
+ * step's initial state q0 and its own input q1, and the third writes q_acc
+ * only in the call's last step.) r is a 5-field scratch in the precision
+ * dtype.
  * Asynchronous. */
 int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
                 const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
