@@ -4,7 +4,7 @@
 // A workgroup owns a TX x TY column tile of the x-y plane and marches its
 // threads up a chunk of z-planes. At output plane z:
 //   - x and y stencils read LDS: the seven fields rho, rho u_a, rho E, p, T
-//     of plane z, and u, v, w from a ring of planes (z-2 .. z+2), each with
+//     of plane z, and u, v, w from a five-plane ring (z-2 .. z+2), each with
 //     a two-point halo (periodic wrap folded into the halo loads);
 //   - z stencils read a per-thread register queue of the seven fields at
 //     planes z-2 .. z+2 of the thread's own column, and the ring for u, v, w;
