@@ -6,7 +6,7 @@ double precision with 32 x 16 tiles and in the single-precision form with
 and at 256^3 (dt = 8.4625e-4) the monitored step of each algorithm the
 benchmark compares there (BL, RA, RS, SN, SS with stored primitives, and
 the fused RA and SS), and at 512^3 the stored-gradient forms (the fused SS
-stage and RS) in the tiling the benchmark times.
+stage in both precisions, and RS) in the tiling the benchmark times.
 
 The oracle cannot advance 2^27 points in seconds, but a step's result on a
 few z-planes depends only on six planes either side of them, so sampled
@@ -70,10 +70,13 @@ def test_512_monitored_fused_step_sampled_planes():
     torch.cuda.empty_cache()
 
 
-def test_512_monitored_fused_step_f32_form_sampled_planes():
-    tune = {"fuse": 1, "block_y": 8, "zchunk": 64}
-    print(f"case fullsize fused monitored step f32 {N} {tune}", flush=True)
-    s = nsf.Solver((N, N, N), PHYS, "SN", "f32", tune=tune)
+@pytest.mark.parametrize("variant,tune", [("SN", {"fuse": 1, "block_y": 8, "zchunk": 64}),
+                                          ("SS", {"fuse": 1})])
+def test_512_monitored_fused_step_f32_form_sampled_planes(variant, tune):
+    # the fused SN stage as the benchmark times it, and the fused SS stage
+    # (its primitive and gradient kernel in the large-grid tiling)
+    print(f"case fullsize fused monitored step f32 {variant} {N} {tune}", flush=True)
+    s = nsf.Solver((N, N, N), PHYS, variant, "f32", tune=tune)
     s.init(W.tgv_pointwise(1610))
     dt = W.tgv_dt(N)
     slabs = {k0: _planes(s.q_acc, k0 - 6, k1 + 6) for k0, k1 in SAMPLES}
