@@ -209,11 +209,26 @@ static void launch_pg(const GradArgs<T>& a, int gmask, const T* q, T* prim, T* g
 // while the grid has fewer tiles than the GPU has CUs (256^3: 0.53 ms
 // against 0.55 ms for the large tiles; 128^3: 32-plane chunks, 0.074 ms
 // against 0.101 ms for 64).
+// Compute units of the current device (256 on a whole MI355X), looked up once
+// per device.
+static int device_cus() {
+    static int cus[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cus[dev] == 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+            n = 256;
+        cus[dev] = n;
+    }
+    return cus[dev];
+}
+
 template <typename T>
 void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
                           int gmask, hipStream_t s) {
     TimerScope ts("ss_prims_grad", s);
-    constexpr int kCUs = 256;
+    const int kCUs = device_cus();
     GradArgs<T> a;
     a.d = d;
     a.c = c;
