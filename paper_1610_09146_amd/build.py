@@ -22,12 +22,12 @@ SOURCES = ["nsf_api.cpp", "nsf_pointwise.hip", "nsf_naive.hip", "nsf_bl.hip", "n
            "nsf_zsweep.hip", "nsf_zsweep_rc.hip", "nsf_batch.cpp", "nsf_grad.hip",
            "nsf_tune.cpp"]
 
-# Per-unit flags. The z-marching kernels without recomputation (SN, SS,
-# their fused stages and the batched SN stage) are scheduled with the AMDGPU
+# Per-unit flags. The z-marching kernels other than RA (SN, SS, RS, the fused
+# stages and the batched SN stage) are scheduled with the AMDGPU
 # register-pressure trackers: same instructions, a schedule that runs the
-# fused SN stage about 1% and the fused SS stage about 7% faster at 512^3.
-# The recompute forms (nsf_zsweep_rc.hip) keep the default, under which they
-# do not spill.
+# fused SN stage about 1%, the fused SS stage about 7% and the RS residual
+# about 14% faster at 512^3. The RA kernels (nsf_zsweep_rc.hip) keep the
+# default, under which they spill less.
 UNIT_FLAGS = {"nsf_zsweep.hip": ["-mllvm", "-amdgpu-use-amdgpu-trackers=1"]}
 
 CFLAGS = [

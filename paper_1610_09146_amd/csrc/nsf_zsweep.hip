@@ -1592,12 +1592,14 @@ void launch_tiles(const ZArgs<T>& a0, int zchunk, hipStream_t s) {
 
 }  // namespace
 
-// The recompute instantiations (RA, RS) are compiled in a unit of their own
-// (nsf_zsweep_rc.hip includes this file with NSF_ZSWEEP_RC_UNIT defined), so
-// that each unit can take the scheduler setting that suits its kernels: the
-// other forms are scheduled with the AMDGPU register-pressure trackers
-// (-1% on the fused SN stage, -7% on the fused SS stage at 512^3), which
-// make the recompute tiles spill (80 B per lane in the fused RA stage, +21%).
+// The RA instantiations (recompute, no stored gradients) are compiled in a
+// unit of their own (nsf_zsweep_rc.hip includes this file with
+// NSF_ZSWEEP_RC_UNIT defined), so that each unit can take the scheduler
+// setting that suits its kernels: the other forms, RS included, are
+// scheduled with the AMDGPU register-pressure trackers (-1% on the fused SN
+// stage, -7% on the fused SS stage, -14% on the RS residual at 512^3, whose
+// spills halve), which make the RA tiles spill more (80 B per lane in the
+// fused RA stage, +21%).
 template <typename T, int TY, bool FUSED, bool SS, bool MON, int GM>
 void launch_tiles_rc(const ZArgs<T>& a, int zchunk, hipStream_t s);
 template <typename T, int TY>
@@ -1626,7 +1628,7 @@ hipError_t batch_occupancy_rc(int* nb) {
                                                         kTX * TY, 0);
 }
 
-// RA residual, fused RA stage (monitored or not), RS residual per store set
+// RA residual, fused RA stage (monitored or not), batched RA stage
 #define NSF_RC_INST(T, TY)                                                                      \
     template void launch_tiles_rc<T, TY, false, false, false, kGradAll>(const ZArgs<T>&, int,    \
                                                                         hipStream_t);           \
@@ -1634,12 +1636,6 @@ hipError_t batch_occupancy_rc(int* nb) {
                                                                       hipStream_t);             \
     template void launch_tiles_rc<T, TY, true, false, false, kGradAll>(const ZArgs<T>&, int,     \
                                                                        hipStream_t);            \
-    template void launch_tiles_rc<T, TY, false, true, false, kGradAll>(const ZArgs<T>&, int,     \
-                                                                       hipStream_t);            \
-    template void launch_tiles_rc<T, TY, false, true, false, kGradDiag>(const ZArgs<T>&, int,    \
-                                                                        hipStream_t);           \
-    template void launch_tiles_rc<T, TY, false, true, false, kGradPlane>(const ZArgs<T>&, int,   \
-                                                                         hipStream_t);          \
     template void launch_batch_rc<T, TY>(dim3, const BatchDesc<T>*, const int2*, const int*,     \
                                          int*, int, int, hipStream_t);                          \
     template hipError_t batch_occupancy_rc<T, TY>(int*);
@@ -1690,8 +1686,8 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
 template <typename T, int GM>
 void launch_ss_set(const ZArgs<T>& a, int zchunk, int tile_y, hipStream_t s, bool recompute) {
     if (recompute) {
-        if (tile_y == 16) launch_tiles_rc<T, 16, false, true, false, GM>(a, zchunk, s);
-        else launch_tiles_rc<T, 8, false, true, false, GM>(a, zchunk, s);
+        if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, true, GM>(a, zchunk, s);
+        else launch_tiles<T, kTX, 8, false, true, false, true, GM>(a, zchunk, s);
     } else {
         if (tile_y == 16) launch_tiles<T, kTX, 16, false, true, false, false, GM>(a, zchunk, s);
         else launch_tiles<T, kTX, 8, false, true, false, false, GM>(a, zchunk, s);
