@@ -121,6 +121,7 @@ struct Layout {
     int nderiv = 0;
     bool fused = false;     // fused SN / RA stages
     bool ss_fused = false;  // fused SS stages
+    bool pg_mon = false;    // SS / RS monitor folded into the first stage's gradient pass
 };
 
 int zchunk_of(const Dims& d, const nsf_tuning* tune) {
@@ -166,6 +167,13 @@ bool wants_fused(int variant, const nsf_tuning* tune) {
 // SS with the stage update applied in the residual kernel's epilogue
 bool wants_ss_fused(int variant, const nsf_tuning* tune) {
     return variant == NSF_SS && tune && tune->fuse && !tune->naive;
+}
+
+// Double-precision tiled SS / RS: the monitored step takes the kinetic energy
+// and enstrophy of its input from the first stage's primitive and gradient
+// pass instead of a separate diagnostics pass.
+bool pg_monitor(int variant, int precision, const nsf_tuning* tune) {
+    return (variant == NSF_SS || variant == NSF_RS) && precision == NSF_F64 && !(tune && tune->naive);
 }
 
 bool is_variant(int v) { return v >= NSF_BL && v <= NSF_AUTO; }
@@ -215,12 +223,16 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     L.qb = L.fused ? L.prim : off;
     L.qc = off;
     off = align_up(off + (L.fused || L.ss_fused ? 5 * d.npts * es : 0));
-    // per-tile (KE, enstrophy) sums of the monitored first stage
+    // per-tile (KE, enstrophy) sums of the monitored first stage: the fused
+    // SN / RA stage's tiles, or the double-precision SS / RS primitive and
+    // gradient kernel's
+    L.pg_mon = pg_monitor(variant, precision, tune);
     L.mon = off;
     off = align_up(off + (L.fused ? 2 * sizeof(double) *
                                         (size_t)sweep_tiles(d, zchunk_of(d, tune),
                                                             tile_y_of(d, tune, (int)es))
-                                  : 0));
+                          : L.pg_mon ? 2 * sizeof(double) * (size_t)ss_prims_grad_tiles(d)
+                                     : 0));
     L.diag_partial = off;
     off = align_up(off + diag_partial_count(d) * NSF_NDIAG * sizeof(double));
     L.diag_out = off;
@@ -265,7 +277,7 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 // One residual evaluation r = R(q) with algorithm `variant`.
 template <typename T>
 int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tune, const T* q,
-             T* r, char* work, const Layout& L, hipStream_t s) {
+             T* r, char* work, const Layout& L, hipStream_t s, double* mpart = nullptr) {
     (void)tune;
     const Coef<T> c = make_coef<T>(d, ph->Re, ph->Ma, ph->Pr, ph->gamma);
     T* prim = (T*)(work + L.prim);
@@ -326,7 +338,7 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
             } else {
                 // the primitive and gradient loops in one pass (same values)
                 const int gm = gmask_of(d, variant, tune);
-                launch_ss_prims_grad<T>(d, c, q, prim, grad, gm, s);
+                launch_ss_prims_grad<T>(d, c, q, prim, grad, gm, s, mpart);
                 launch_ss_zsweep<T>(d, c, q, prim, grad, r, zchunk_of(d, tune),
                                     tile_y_of(d, tune, sizeof(T)), s, variant == NSF_RS, gm);
             }
@@ -396,8 +408,9 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
         const int gm = gmask_of(d, variant, tune);
         const int zc = zchunk_of(d, tune);
         const int ty = tile_y_of(d, tune, sizeof(T));
+        double* mpart = (double*)(work + L.mon);
         for (int step = 0; step < nsteps; ++step) {
-            if (monitor) {
+            if (monitor && !L.pg_mon) {
                 double* dout = (double*)(work + L.diag_out);
                 launch_diag<T>(d, cd, q, (double*)(work + L.diag_partial), dout, s);
                 hipError_t e = hipMemcpyAsync(monitor + 2 * step, dout, 2 * sizeof(double),
@@ -409,14 +422,18 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
                 sc.a_dt = st < 2 ? A[st] * dt : 0.0;
                 sc.b_dt = B[st] * dt;
                 sc.last = st == 2;
-                launch_ss_prims_grad<T>(d, c, in[st], prim, grad, gm, s);
+                const bool mon = monitor && L.pg_mon && st == 0;
+                launch_ss_prims_grad<T>(d, c, in[st], prim, grad, gm, s, mon ? mpart : nullptr);
+                if (mon)
+                    launch_monitor_final(mpart, ss_prims_grad_tiles(d), inv_n, monitor + 2 * step, s);
                 launch_ss_fused<T>(d, c, in[st], prim, grad, out[st], qacc, sc, zc, ty, s, gm);
             }
         }
         return check_hip("rk_step launch");
     }
+    double* mpart = (double*)(work + L.mon);
     for (int step = 0; step < nsteps; ++step) {
-        if (monitor) {
+        if (monitor && !L.pg_mon) {
             // the diagnostics pass writes NDIAG means; KE and enstrophy lead
             double* dout = (double*)(work + L.diag_out);
             launch_diag<T>(d, cd, q, (double*)(work + L.diag_partial), dout, s);
@@ -425,8 +442,12 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
             if (e != hipSuccess) return fail(NSF_EHIP, "monitor copy: %s", hipGetErrorString(e));
         }
         for (int st = 0; st < 3; ++st) {
-            int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s);
+            // SS / RS (double precision): the first stage's gradient pass
+            // also sums the monitor of its input state
+            const bool mon = monitor && L.pg_mon && st == 0;
+            int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s, mon ? mpart : nullptr);
             if (rc) return rc;
+            if (mon) launch_monitor_final(mpart, ss_prims_grad_tiles(d), inv_n, monitor + 2 * step, s);
             StageCoef sc;
             sc.a_dt = st < 2 ? A[st] * dt : 0.0;
             sc.b_dt = B[st] * dt;

@@ -73,15 +73,23 @@ struct GradArgs {
 // instead of the 80 + 96 of the two loops. The in-plane differences of the
 // centre plane come from the LDS ring, the z differences from a register
 // queue of the own column's velocity (planes z-2 .. z+2).
-template <typename T, int GM, int TY>
+// MON (double precision): the tile also sums the kinetic energy and the
+// enstrophy of its points, 1/2 rho |u|^2 and 1/2 rho |omega|^2 with omega
+// from the same fourth-order velocity gradients (Section 3 diagnostics), in
+// plane order per thread, then over the block in a fixed order, into
+// mpart[2 * tile]: the monitor of a step whose first stage this is, without
+// a separate diagnostics pass.
+template <typename T, int GM, int TY, bool MON>
 __global__ void __launch_bounds__(32 * TY) k_ss_prims_grad(GradArgs<T> A, const T* __restrict__ q,
                                                            T* __restrict__ prim,
-                                                           T* __restrict__ grad) {
+                                                           T* __restrict__ grad,
+                                                           double* __restrict__ mpart) {
     using G = PgTile<TY>;
     constexpr int kTX = G::TX, kLX = G::LX, kNPL = G::NPL, kNHALO = G::NHALO;
     auto slot = [](int a, int b) { return __builtin_popcount(GM & ((1 << (3 * a + b)) - 1)); };
     auto stored = [](int a, int b) { return (GM >> (3 * a + b)) & 1; };
     __shared__ T sV[kRing * 3 * kNPL];
+    __shared__ double sM[MON ? 2 * (G::NT / 64) : 1];
     const Dims d = A.d;
     const Coef<T> c = A.c;
     const size_t n = d.npts;
@@ -125,8 +133,9 @@ __global__ void __launch_bounds__(32 * TY) k_ss_prims_grad(GradArgs<T> A, const 
         return r;
     };
     // velocity of plane zz into its ring slot and the own column's queue
-    // entry vq; the primitives of the chunk's own planes out
-    auto enter = [&](int zz, const Raw& r, T vq[3]) {
+    // entry vq (density into rq); the primitives of the chunk's own planes out
+    auto enter = [&](int zz, const Raw& r, T vq[3], T& rq) {
+        rq = r.own[0];
         T* V = sV + pmodg(zz, kRing) * 3 * kNPL;
         const Prim<T> P = primitives(r.own[0], r.own[1], r.own[2], r.own[3], r.own[4], c);
         vq[0] = P.u;
@@ -151,64 +160,88 @@ __global__ void __launch_bounds__(32 * TY) k_ss_prims_grad(GradArgs<T> A, const 
         }
     };
     T vq[5][3];  // own column's velocity, planes z-2 .. z+2
+    T rq[5];     // and its density
 #pragma unroll
-    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s), vq[s + 1]);
+    for (int s = 0; s < 4; ++s) enter(z0 - 2 + s, fetch(z0 - 2 + s), vq[s + 1], rq[s + 1]);
     Raw nxt = fetch(z0 + 2);
     const T a1x = c.a1[0], a2x = c.a2[0], a1y = c.a1[1], a2y = c.a2[1];
     const T a1z = c.a1[2], a2z = c.a2[2];
+    double mke = 0.0, mens = 0.0;
     for (int z = z0; z < z1; ++z) {
         const Raw cur = nxt;
         if (z + 1 < z1) nxt = fetch(z + 3);
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int s = 0; s < 4; ++s) {
+            rq[s] = rq[s + 1];
 #pragma unroll
             for (int a = 0; a < 3; ++a) vq[s][a] = vq[s + 1][a];
-        enter(z + 2, cur, vq[4]);
+        }
+        enter(z + 2, cur, vq[4], rq[4]);
         __syncthreads();
         if (active) {
             const size_t o = (size_t)z * plane + col;
             const T* Vc = sV + pmodg(z, kRing) * 3 * kNPL;
+            T g[3][3];  // g[a][b] = D_b u_a (the monitor needs all nine)
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const T* F = Vc + a * kNPL;
-                if (stored(a, 0))
-                    st_nt(a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]),
-                          grad + slot(a, 0) * n + o);
-                if (stored(a, 1))
-                    st_nt(a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]),
-                          grad + slot(a, 1) * n + o);
-                if (stored(a, 2))
-                    st_nt(a1z * (vq[3][a] - vq[1][a]) + a2z * (vq[4][a] - vq[0][a]),
-                          grad + slot(a, 2) * n + o);
+                g[a][0] = a1x * (F[own + 1] - F[own - 1]) + a2x * (F[own + 2] - F[own - 2]);
+                g[a][1] = a1y * (F[own + kLX] - F[own - kLX]) + a2y * (F[own + 2 * kLX] - F[own - 2 * kLX]);
+                g[a][2] = a1z * (vq[3][a] - vq[1][a]) + a2z * (vq[4][a] - vq[0][a]);
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+                    if (stored(a, b)) st_nt(g[a][b], grad + slot(a, b) * n + o);
             }
+            if constexpr (MON) {
+                const double rho = rq[2], u = vq[2][0], v = vq[2][1], w = vq[2][2];
+                const double ox = g[2][1] - g[1][2], oy = g[0][2] - g[2][0], oz = g[1][0] - g[0][1];
+                mke += 0.5 * rho * (u * u + v * v + w * w);
+                mens += 0.5 * rho * (ox * ox + oy * oy + oz * oz);
+            }
+        }
+    }
+    if constexpr (MON) {
+        // fixed order: wave shuffles, then the waves in order
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            mke += __shfl_down(mke, off, 64);
+            mens += __shfl_down(mens, off, 64);
+        }
+        if ((tid & 63) == 0) {
+            sM[2 * (tid >> 6)] = mke;
+            sM[2 * (tid >> 6) + 1] = mens;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double x = 0.0, y = 0.0;
+            for (int w = 0; w < G::NT / 64; ++w) {
+                x += sM[2 * w];
+                y += sM[2 * w + 1];
+            }
+            mpart[2 * t] = x;
+            mpart[2 * t + 1] = y;
         }
     }
 }
 
 }  // namespace
 
-template <typename T, int TY>
+template <typename T, int TY, bool MON>
 static void launch_pg(const GradArgs<T>& a, int gmask, const T* q, T* prim, T* grad,
-                      hipStream_t s) {
+                      double* mpart, hipStream_t s) {
     const int tz = (a.d.nz + a.zchunk - 1) / a.zchunk;
     const dim3 grid(a.tiles_x * a.tiles_y * tz), block(32 * TY);
     if (gmask == kGradDiag)
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradDiag, TY>), grid, block, 0, s, a, q, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradDiag, TY, MON>), grid, block, 0, s, a, q, prim,
+                           grad, mpart);
     else if (gmask == kGradPlane)
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradPlane, TY>), grid, block, 0, s, a, q, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradPlane, TY, MON>), grid, block, 0, s, a, q, prim,
+                           grad, mpart);
     else
-        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradAll, TY>), grid, block, 0, s, a, q, prim, grad);
+        hipLaunchKernelGGL((k_ss_prims_grad<T, kGradAll, TY, MON>), grid, block, 0, s, a, q, prim,
+                           grad, mpart);
 }
 
-// Tiles: on large grids 32 x 32 with 128-plane chunks, while that leaves four
-// tiles per CU (one workgroup each: its four-plane ring takes 124 KB in
-// double precision). Their halo and chunk preamble re-read q 1.13 times at
-// 512^3, against 1.44 times for 32 x 16 tiles with 64-plane chunks (3.90
-// against 4.12 ms per launch). Smaller grids keep 32 x 8 tiles (three
-// workgroups per CU) with chunks of at most 64 planes, halved down to 16
-// while the grid has fewer tiles than the GPU has CUs (256^3: 0.53 ms
-// against 0.55 ms for the large tiles; 128^3: 32-plane chunks, 0.074 ms
-// against 0.101 ms for 64).
 // Compute units of the current device (256 on a whole MI355X), looked up once
 // per device.
 static int device_cus() {
@@ -224,31 +257,62 @@ static int device_cus() {
     return cus[dev];
 }
 
+// Tiles: on large grids 32 x 32 with 128-plane chunks, while that leaves four
+// tiles per CU (one workgroup each: its four-plane ring takes 124 KB in
+// double precision). Their halo and chunk preamble re-read q 1.13 times at
+// 512^3, against 1.44 times for 32 x 16 tiles with 64-plane chunks (3.90
+// against 4.12 ms per launch). Smaller grids keep 32 x 8 tiles (three
+// workgroups per CU) with chunks of at most 64 planes, halved down to 16
+// while the grid has fewer tiles than the GPU has CUs (256^3: 0.53 ms
+// against 0.55 ms for the large tiles; 128^3: 32-plane chunks, 0.074 ms
+// against 0.101 ms for 64).
 template <typename T>
-void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
-                          int gmask, hipStream_t s) {
-    TimerScope ts("ss_prims_grad", s);
-    const int kCUs = device_cus();
-    GradArgs<T> a;
+static GradArgs<T> pg_plan(const Dims& d, int* ty) {
+    const int cus = device_cus();
+    GradArgs<T> a{};
     a.d = d;
-    a.c = c;
     a.tiles_x = (d.nx + 31) / 32;
-    if (a.tiles_x * ((d.ny + 31) / 32) * (d.nz / 128) >= 4 * kCUs) {
+    if (a.tiles_x * ((d.ny + 31) / 32) * (d.nz / 128) >= 4 * cus) {
+        *ty = 32;
         a.tiles_y = (d.ny + 31) / 32;
         a.zchunk = 128;
-        launch_pg<T, 32>(a, gmask, q, prim, grad, s);
     } else {
+        *ty = 8;
         a.tiles_y = (d.ny + 7) / 8;
         int zc = 64;
-        while (zc > 16 && a.tiles_x * a.tiles_y * ((d.nz + zc - 1) / zc) < kCUs) zc /= 2;
+        while (zc > 16 && a.tiles_x * a.tiles_y * ((d.nz + zc - 1) / zc) < cus) zc /= 2;
         a.zchunk = d.nz < zc ? d.nz : zc;
-        launch_pg<T, 8>(a, gmask, q, prim, grad, s);
     }
+    return a;
+}
+
+int ss_prims_grad_tiles(const Dims& d) {
+    int ty;
+    const GradArgs<double> a = pg_plan<double>(d, &ty);
+    return a.tiles_x * a.tiles_y * ((d.nz + a.zchunk - 1) / a.zchunk);
+}
+
+template <typename T>
+void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
+                          int gmask, hipStream_t s, double* mpart) {
+    TimerScope ts("ss_prims_grad", s);
+    int ty;
+    GradArgs<T> a = pg_plan<T>(d, &ty);
+    a.c = c;
+    if constexpr (sizeof(T) == 8) {
+        if (mpart) {
+            if (ty == 32) launch_pg<T, 32, true>(a, gmask, q, prim, grad, mpart, s);
+            else launch_pg<T, 8, true>(a, gmask, q, prim, grad, mpart, s);
+            return;
+        }
+    }
+    if (ty == 32) launch_pg<T, 32, false>(a, gmask, q, prim, grad, nullptr, s);
+    else launch_pg<T, 8, false>(a, gmask, q, prim, grad, nullptr, s);
 }
 
 template void launch_ss_prims_grad<float>(const Dims&, const Coef<float>&, const float*, float*,
-                                          float*, int, hipStream_t);
+                                          float*, int, hipStream_t, double*);
 template void launch_ss_prims_grad<double>(const Dims&, const Coef<double>&, const double*,
-                                           double*, double*, int, hipStream_t);
+                                           double*, double*, int, hipStream_t, double*);
 
 }  // namespace nsf

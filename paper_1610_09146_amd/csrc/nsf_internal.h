@@ -174,10 +174,14 @@ void launch_ss_fused(const Dims& d, const Coef<T>& c, const T* q, const T* prim,
                      T* qout, double* qacc, const StageCoef& sc, int zchunk, int tile_y,
                      hipStream_t s, int gmask);
 // SS / RS primitive and gradient loops in one pass (z-marching tiles): prim =
-// u, v, w, p, T of q (eqs (9)-(10)) and the store set's G_ab = D_b u_a.
+// u, v, w, p, T of q (eqs (9)-(10)) and the store set's G_ab = D_b u_a. With
+// mpart (double precision only) each tile also writes its kinetic-energy and
+// enstrophy sums to mpart[2 * tile] (ss_prims_grad_tiles(d) tiles), for
+// launch_monitor_final.
 template <typename T>
 void launch_ss_prims_grad(const Dims& d, const Coef<T>& c, const T* q, T* prim, T* grad,
-                          int gmask, hipStream_t s);
+                          int gmask, hipStream_t s, double* mpart = nullptr);
+int ss_prims_grad_tiles(const Dims& d);
 // Fused stage with no derivative arrays (RA with recompute = true, SN
 // otherwise): primitives recomputed in-tile, residual, and the RK stage
 // update: qout = q_acc + A dt R (or q_acc_new on the last substep),

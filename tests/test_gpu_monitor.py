@@ -51,6 +51,7 @@ CASES = [
     ("RA", "f64", None),
     ("SN", "f64", None),
     ("SS", "f64", None),
+    ("SS", "f64", {"fuse": 1}),
     ("RS", "f64", None),
     ("BL", "f64", None),
     ("SS", "f32", None),
