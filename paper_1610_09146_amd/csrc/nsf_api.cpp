@@ -122,6 +122,7 @@ struct Layout {
     bool fused = false;     // fused SN / RA stages
     bool ss_fused = false;  // fused SS stages
     bool pg_mon = false;    // SS / RS monitor folded into the first stage's gradient pass
+    bool zs_mon = false;    // SN / RA (stored primitives) monitor folded into its residual pass
 };
 
 int zchunk_of(const Dims& d, const nsf_tuning* tune) {
@@ -176,6 +177,13 @@ bool pg_monitor(int variant, int precision, const nsf_tuning* tune) {
     return (variant == NSF_SS || variant == NSF_RS) && precision == NSF_F64 && !(tune && tune->naive);
 }
 
+// Double-precision tiled SN / RA with stored primitives: the same from the
+// first stage's residual pass.
+bool zs_monitor(int variant, int precision, const nsf_tuning* tune) {
+    return (variant == NSF_SN || variant == NSF_RA) && precision == NSF_F64 &&
+           !(tune && (tune->naive || tune->fuse));
+}
+
 bool is_variant(int v) { return v >= NSF_BL && v <= NSF_AUTO; }
 
 // NSF_AUTO -> the recorded (or default) algorithm and tuning; `store`
@@ -227,10 +235,11 @@ Layout layout_for(const Dims& d, int variant, int precision, const nsf_tuning* t
     // SN / RA stage's tiles, or the double-precision SS / RS primitive and
     // gradient kernel's
     L.pg_mon = pg_monitor(variant, precision, tune);
+    L.zs_mon = zs_monitor(variant, precision, tune);
     L.mon = off;
-    off = align_up(off + (L.fused ? 2 * sizeof(double) *
-                                        (size_t)sweep_tiles(d, zchunk_of(d, tune),
-                                                            tile_y_of(d, tune, (int)es))
+    off = align_up(off + (L.fused || L.zs_mon ? 2 * sizeof(double) *
+                                                  (size_t)sweep_tiles(d, zchunk_of(d, tune),
+                                                                      tile_y_of(d, tune, (int)es))
                           : L.pg_mon ? 2 * sizeof(double) * (size_t)ss_prims_grad_tiles(d)
                                      : 0));
     L.diag_partial = off;
@@ -326,7 +335,7 @@ int rhs_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* t
             launch_prims<T>(d, c, q, prim, s);
             if (tune && tune->naive) launch_ra_naive<T>(d, c, q, prim, r, s);
             else launch_ra_zsweep<T>(d, c, q, prim, r, zchunk_of(d, tune), tile_y_of(d, tune, sizeof(T)), s,
-                                     variant == NSF_RA);
+                                     variant == NSF_RA, mpart);
             break;
         case NSF_SS:
         case NSF_RS: {
@@ -432,8 +441,11 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
         return check_hip("rk_step launch");
     }
     double* mpart = (double*)(work + L.mon);
+    const bool folded = L.pg_mon || L.zs_mon;
+    const int mon_tiles = L.pg_mon ? ss_prims_grad_tiles(d)
+                                   : sweep_tiles(d, zchunk_of(d, tune), tile_y_of(d, tune, sizeof(T)));
     for (int step = 0; step < nsteps; ++step) {
-        if (monitor && !L.pg_mon) {
+        if (monitor && !folded) {
             // the diagnostics pass writes NDIAG means; KE and enstrophy lead
             double* dout = (double*)(work + L.diag_out);
             launch_diag<T>(d, cd, q, (double*)(work + L.diag_partial), dout, s);
@@ -442,12 +454,13 @@ int rk_impl(const Dims& d, const nsf_phys* ph, int variant, const nsf_tuning* tu
             if (e != hipSuccess) return fail(NSF_EHIP, "monitor copy: %s", hipGetErrorString(e));
         }
         for (int st = 0; st < 3; ++st) {
-            // SS / RS (double precision): the first stage's gradient pass
-            // also sums the monitor of its input state
-            const bool mon = monitor && L.pg_mon && st == 0;
+            // double precision, SS / RS and SN / RA with stored primitives:
+            // the first stage's gradient or residual pass also sums the
+            // monitor of its input state
+            const bool mon = monitor && folded && st == 0;
             int rc = rhs_impl<T>(d, ph, variant, tune, q, r, work, L, s, mon ? mpart : nullptr);
             if (rc) return rc;
-            if (mon) launch_monitor_final(mpart, ss_prims_grad_tiles(d), inv_n, monitor + 2 * step, s);
+            if (mon) launch_monitor_final(mpart, mon_tiles, inv_n, monitor + 2 * step, s);
             StageCoef sc;
             sc.a_dt = st < 2 ? A[st] * dt : 0.0;
             sc.b_dt = B[st] * dt;

@@ -153,10 +153,13 @@ int batch_blocks_per_cu(int tile_y, bool recompute);
 // Residual from stored primitives, no derivative arrays: recompute = true is
 // the recompute-all algorithm RA (every derivative formed where a term uses
 // it, equation by equation), false the store-none algorithm SN (every
-// derivative formed once per point into thread-local values).
+// derivative formed once per point into thread-local values). With mpart
+// (double precision only) each tile also writes the kinetic-energy and
+// enstrophy sums of its points to mpart[2 * tile] (sweep_tiles tiles).
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, int tile_y, hipStream_t s, bool recompute);
+                      int zchunk, int tile_y, hipStream_t s, bool recompute,
+                      double* mpart = nullptr);
 // Residual with the velocity gradients and D_a(G_cc) read from the nine
 // stored gradient arrays: recompute = true is the recompute-some algorithm
 // RS (the other derivatives formed where used, equation by equation), false

@@ -676,7 +676,7 @@ __device__ __forceinline__ void zsweep_tile(const ZArgs<T>& A, int t, T* __restr
     // not.
     constexpr bool RP = FUSED && !SS;
     static_assert(!(FUSED && SS && (MON || RC)), "the fused stored-gradient stage is SS, unmonitored");
-    static_assert(!MON || FUSED, "the monitor is part of the fused stage");
+    static_assert(!MON || !SS, "the stored-gradient forms sum the monitor in their gradient pass");
     constexpr bool HR = halo_ring<T, TY, FUSED, MON, SS>();
     constexpr int HF = halo_fields<SS>();
     // Lean form of the fused stage: no branch between the prefetch and the
@@ -1628,10 +1628,12 @@ hipError_t batch_occupancy_rc(int* nb) {
                                                         kTX * TY, 0);
 }
 
-// RA residual, fused RA stage (monitored or not), batched RA stage
+// RA residual and fused RA stage (monitored or not), batched RA stage
 #define NSF_RC_INST(T, TY)                                                                      \
     template void launch_tiles_rc<T, TY, false, false, false, kGradAll>(const ZArgs<T>&, int,    \
                                                                         hipStream_t);           \
+    template void launch_tiles_rc<T, TY, false, false, true, kGradAll>(const ZArgs<T>&, int,     \
+                                                                       hipStream_t);            \
     template void launch_tiles_rc<T, TY, true, false, true, kGradAll>(const ZArgs<T>&, int,      \
                                                                       hipStream_t);             \
     template void launch_tiles_rc<T, TY, true, false, false, kGradAll>(const ZArgs<T>&, int,     \
@@ -1666,7 +1668,7 @@ void tile_counts(const Dims& d, int zchunk, int tile_y, int* tx, int* ty, int* t
 
 template <typename T>
 void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim, T* r,
-                      int zchunk, int tile_y, hipStream_t s, bool recompute) {
+                      int zchunk, int tile_y, hipStream_t s, bool recompute, double* mpart) {
     TimerScope ts(recompute ? "ra_zsweep" : "sn_zsweep", s);
     ZArgs<T> a{};
     a.d = d;
@@ -1674,6 +1676,21 @@ void launch_ra_zsweep(const Dims& d, const Coef<T>& c, const T* q, const T* prim
     a.q = q;
     a.prim = prim;
     a.r = r;
+    a.mpart = mpart;
+    // the monitored build (double precision): each tile also sums the
+    // kinetic energy and enstrophy of its input points into mpart
+    if constexpr (sizeof(T) == 8) {
+        if (mpart) {
+            if (recompute) {
+                if (tile_y == 16) launch_tiles_rc<T, 16, false, false, true, kGradAll>(a, zchunk, s);
+                else launch_tiles_rc<T, 8, false, false, true, kGradAll>(a, zchunk, s);
+            } else {
+                if (tile_y == 16) launch_tiles<T, kTX, 16, false, false, true>(a, zchunk, s);
+                else launch_tiles<T, kTX, 8, false, false, true>(a, zchunk, s);
+            }
+            return;
+        }
+    }
     if (recompute) {
         if (tile_y == 16) launch_tiles_rc<T, 16, false, false, false, kGradAll>(a, zchunk, s);
         else launch_tiles_rc<T, 8, false, false, false, kGradAll>(a, zchunk, s);
@@ -1838,7 +1855,7 @@ void launch_ra_fused(const Dims& d, const Coef<T>& c, const T* q, T* qout, doubl
                                      int, int, hipStream_t, bool, int);                       \
     template int batch_blocks_per_cu<T>(int, bool);                                           \
     template void launch_ra_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*, T*,  \
-                                      int, int, hipStream_t, bool);                         \
+                                      int, int, hipStream_t, bool, double*);                \
     template void launch_ss_zsweep<T>(const Dims&, const Coef<T>&, const T*, const T*,      \
                                       const T*, T*, int, int, hipStream_t, bool, int);      \
     template void launch_ss_fused<T>(const Dims&, const Coef<T>&, const T*, const T*,       \

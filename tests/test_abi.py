@@ -60,7 +60,9 @@ def test_workspace_sizes(nsf):
     sizes = {v: nsf.workspace_bytes((n, n, n), v, "f64") for v in ("BL", "RA", "SS")}
     assert sizes["RA"] >= 5 * npts * 8
     assert sizes["SS"] - sizes["RA"] >= 9 * npts * 8
-    assert sizes["BL"] - sizes["RA"] >= 61 * npts * 8
+    # (RA and SS also hold their monitor's per-tile partial sums: two doubles
+    # per tile, a few KB)
+    assert sizes["BL"] - sizes["RA"] >= 61 * npts * 8 - 64 * 1024
     s32 = nsf.workspace_bytes((n, n, n), "RA", "f32")
     assert s32 >= 5 * npts * 4 and s32 < sizes["RA"]
     # the fused form adds one rotating state (the other shares the primitives)
