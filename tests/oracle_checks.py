@@ -272,7 +272,7 @@ def stage_model_mismatch(phys, prec="d"):
     return float(np.abs((got - full[:, idx[6:8]]).astype(np.float64)).max())
 
 
-# --------------------------------------------------------------- verdicts
+# ---------------------------------------------------------- pass or fail
 CONT_RATIO_BOUNDS = ((12.5, 18.0), (14.5, 17.5))
 
 
