@@ -126,9 +126,15 @@ def _monitored_step_sampled_planes(variant, tune, n):
         return t[:, [(k % n) for k in range(k0, k1)]].cpu().numpy()
 
     slabs = {k0: planes(s.q, k0 - 6, k1 + 6) for k0, k1 in samples}
+    d0 = s.diagnostics()
     mon = torch.zeros(4, dtype=torch.float64, device="cuda")
     s.step_monitored(dt, 1, mon)
     torch.cuda.synchronize()
+    # the monitor (summed inside the first stage's kernels, or by the
+    # diagnostics pass) holds the kinetic energy and enstrophy of the input
+    # state, as nsf_diagnostics reports them
+    got = mon.cpu().numpy()[:2]
+    assert np.all(np.abs(got - d0[:2]) <= 1e-13 * np.abs(d0[:2])), (got, d0[:2])
     for k0, k1 in samples:
         q0 = slabs[k0]
         base = q0[:, 6:-6]
