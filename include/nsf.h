@@ -152,7 +152,8 @@ int nsf_version(void);
 /* Bytes of `work` needed by nsf_rhs / nsf_rk_step / nsf_diagnostics for this
  * grid, algorithm, precision and tuning (tuning may be NULL): primitive
  * fields, stored derivative arrays of the algorithm, the ping-pong state of
- * the fused form, and reduction scratch. Written to *bytes. */
+ * the fused form, the monitor's per-tile sums and reduction scratch.
+ * Written to *bytes. */
 int nsf_workspace_bytes(const nsf_grid *g, int variant, int precision,
                         const nsf_tuning *tune, size_t *bytes);
 
@@ -193,10 +194,13 @@ int nsf_rk_step(const nsf_grid *g, const nsf_phys *phys, int variant, int precis
  * 2 * nsteps doubles, not overlapping the other buffers; entries 2s and
  * 2s+1 receive the grid means of rho|u|^2/2 and rho|omega|^2/2 (omega =
  * curl u by the fourth-order first difference) of the state at the start of
- * step s, the quantities of out[0] and out[1] of nsf_diagnostics. In the
- * fused SN and RA forms the sums are formed inside the first stage's
- * residual kernel from the values it already holds; otherwise a
- * diagnostics pass runs before every step. NSF_EINVAL for a NULL or misaligned monitor.
+ * step s, the quantities of out[0] and out[1] of nsf_diagnostics. The sums
+ * are formed inside the first stage's kernels from the values they already
+ * hold in the fused SN and RA forms, and in double precision also for SS
+ * and RS (their primitive and gradient pass) and for SN and RA with stored
+ * primitives (their residual pass); otherwise (BL, the untiled kernels, the
+ * other single-precision forms) a diagnostics pass runs before every step.
+ * NSF_EINVAL for a NULL or misaligned monitor.
  * Asynchronous. */
 int nsf_rk_step_monitored(const nsf_grid *g, const nsf_phys *phys, int variant, int precision,
                           const nsf_tuning *tune, double dt, int32_t nsteps, void *q,
